@@ -1,0 +1,77 @@
+"""One implicit BDF2 time step solved by Newton-Krylov.
+
+Test infrastructure (oracle); see oracle/__init__.py.
+
+Sec. 4, Eq. NEWTON gives the Newton iteration for an ESDIRK stage: the
+iteration matrix M/(a_ii dt) + dR/dW and the unsteady residual.  With BDF2 in
+place of ESDIRK3 (one step, W^{n+1} from W^n and W^{n-1}):
+
+    R_u(W) = M (3 W - 4 W^n + W^{n-1}) / (2 dt) + R(W),
+    K      = 3/(2 dt) M + dR/dW,
+    Newton: K x = -R_u(W_k),  W_{k+1} = W_k + x.
+
+The preconditioner is built once at W^n and lagged over the whole step (the
+"MFL" option of Sec. 7.3).  Newton stops when ||R_u(W_k)|| <= tol ||R_u(W_0)||
+(relative reading of the paper's nonlinear tolerance) or when ||R_u(W_k)||
+reaches the rounding floor 1e-14 * (3/(2 dt)) ||M W^n|| (the size of the
+unsteady term), at most `max_newton` iterations.  A fresh case has no W^{n-1}; it is taken equal to W^n.
+"""
+import numpy as np
+
+from . import linear as lin
+
+
+class StepStats:
+    def __init__(self):
+        self.newton = 0
+        self.linear_iters = []
+        self.rel_res_true = []
+        self.res_history = []
+
+
+def bdf2_step(D, Wn, Wnm1, dt, precond="pmg", levels=None, restart=40, rtol=1e-8,
+              newton_tol=1e-10, max_newton=5, nu_pre=2, nu_post=2, omega=1.0, coarse_iters=30,
+              max_restarts=20, jvp="exact"):
+    """`jvp` selects the Krylov operator: "exact" (tangent-linear Jacobian
+    action) or "fd" (the finite-difference form of Eq. DG-mf).  The FD form
+    carries a relative error of about sqrt(machine eps) (1e-8..1e-7 here), so
+    relative linear tolerances of 1e-8 and below need the exact action."""
+    a = 3.0 / (2.0 * dt)
+    Wnm1 = Wn if Wnm1 is None else Wnm1
+    W = Wn.copy()
+    RW = D.residual(W)
+    if precond == "pmg":
+        P = lin.PMG(D, W, a, levels if levels is not None else [D.p], nu_pre, nu_post, omega,
+                    coarse_iters, RW=RW)
+    elif precond == "bj":
+        P = lin.BlockJacobi(D, W, a)
+    else:
+        P = None
+    prec = (lambda r: r) if P is None else P.apply
+    st = StepStats()
+
+    def unsteady(W, RW):
+        return D.mass(3.0 * W - 4.0 * Wn + Wnm1) / (2.0 * dt) + RW
+
+    Ru = unsteady(W, RW)
+    r0 = lin.norm(Ru)
+    floor = 1e-14 * a * lin.norm(D.mass(Wn))
+    st.res_history.append(r0)
+    for k in range(max_newton):
+        rk = lin.norm(Ru)
+        if rk <= newton_tol * r0 or rk <= floor:
+            break
+        Wk, RWk = W, RW
+        if jvp == "fd":
+            A = lambda v: lin.jvp_fd(D, Wk, RWk, v, a)
+        else:
+            A = lambda v: lin.jvp_exact(D, Wk, v, a)
+        x, ls = lin.fgmres(A, prec, -Ru, restart, rtol, max_restarts)
+        st.linear_iters.append(ls.iters)
+        st.rel_res_true.append(ls.rel_res_true)
+        W = W + x
+        RW = D.residual(W)
+        Ru = unsteady(W, RW)
+        st.newton += 1
+        st.res_history.append(lin.norm(Ru))
+    return W, st
