@@ -1,0 +1,199 @@
+/*
+ * dg.h -- C ABI of the MI355X (gfx950) implicit modal DG hot path.
+ *
+ * Franciolini, Fidkowski, Crivellini, "Efficient discontinuous Galerkin
+ * implementations and preconditioners for implicit unsteady compressible flow
+ * simulations", arXiv 1812.04789.
+ *
+ * Problem statement followed by this interface:
+ *   semi-discrete system   M dW/dt + R(W) = 0                 (Sec. 3.1)
+ *   Newton systems          K x = b,  K = a M + dR/dW          (Sec. 4 Eq. NEWTON,
+ *                                                              Sec. 5.1 Eq. ODEDG;
+ *                                                              the paper writes
+ *                                                              K x + b = 0)
+ *   matrix-free product     K v ~ a M v + (R(W+hv)-R(W))/h      (Sec. 5.1 Eq. DG-mf)
+ *   p-multigrid V-cycle     Alg. 2 with subspace inheritance   (Sec. 6, 6.1)
+ *   block-Jacobi smoother   element-wise PLU                   (Sec. 6.3)
+ *   flexible GMRES          right preconditioned               (Sec. 6)
+ *
+ * Conventions (all entry points):
+ *  - Vectors are FP64 DEVICE pointers owned by the caller, length dg_ndof(),
+ *    layout W[element][equation][mode]: element e = i + nx*(j + ny*k) of the
+ *    periodic box, equations (rho, rho u, rho v, rho w, rho e0), modes of the
+ *    orthonormal Legendre tensor basis L_a(xi1) L_b(xi2) L_c(xi3),
+ *    L_a(t) = sqrt((2a+1)/2) P_a(t), in hierarchical order (shell
+ *    max(a,b,c), then (a,b,c) lexicographic, a most significant); the modes of
+ *    degree <= q are the first (q+1)^3 of every (element, equation) run.
+ *  - Every call enqueues on the context's HIP stream and returns without
+ *    waiting, except fgmres_step and dg_bdf2_step (which synchronise to test
+ *    convergence and fill their statistics) and dg_create/dg_destroy.
+ *  - The context owns all internal device memory (factors, coarse operators,
+ *    Krylov basis, scratch); nothing it returns must be freed by the caller.
+ *  - Output vectors must not alias inputs (DG_EINVAL).
+ *  - No C++ exception crosses the ABI.  On error the call returns a negative
+ *    dg_status and dg_last_error() describes it.
+ */
+#ifndef DG_MI355X_H
+#define DG_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,      /* bad argument, size, alias or mesh                  */
+    DG_ENOMEM = -2,      /* device allocation failed                           */
+    DG_EHIP = -3,        /* HIP runtime error                                  */
+    DG_ENOCONV = -4,     /* solver did not reach its tolerance (best x kept)   */
+    DG_ENONFINITE = -5,  /* NaN/Inf met in a residual or a Krylov scalar       */
+    DG_ESTATE = -6       /* call order violated (e.g. pmg_apply before setup)  */
+} dg_status;
+
+enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };
+
+/* Periodic structured hexahedral mesh (Sec. 3).  vtx: optional HOST array
+ * [ne][8][3] of trilinear (Q1) element vertices, local vertex v = i+2j+4k at
+ * reference corner (2i-1, 2j-1, 2k-1); NULL gives the straight box.  The
+ * vertex copies of an element across a periodic boundary must differ by the
+ * box period.  Copied at dg_create. */
+typedef struct {
+    int nx, ny, nz;
+    double lo[3], hi[3];
+    const double* vtx;
+} dg_mesh_desc;
+
+/* Gas model (Sec. 2, Eq. NS): gamma, constant viscosity mu (0 = Euler),
+ * Prandtl number Pr, BR2 penalty eta_F (Sec. 3.1 Eq. visc_flux; the paper
+ * requires eta_F > number of element faces). */
+typedef struct {
+    double gamma, mu, Pr, eta;
+} dg_phys;
+
+/* p-multigrid preconditioner (Sec. 6, Alg. 2; Sec. 6.1; Sec. 6.3).
+ *  n_levels       1..4; p_level[0] must equal the context's p and the degrees
+ *                 must decrease.  n_levels == 1 is the single-grid element
+ *                 block-Jacobi preconditioner z = D^-1 r.
+ *  nu_pre/nu_post damped block-Jacobi sweeps x += omega D^-1 (b - K x) per level.
+ *  coarsest_iters right-preconditioned GMRES(BJ) iterations on the coarsest level.
+ *  prec_fine      DG_FP64 or DG_FP32: storage/arithmetic of the level-0 PLU factors.
+ *  prec_coarse    DG_FP64, DG_FP32 or DG_BF16: storage of coarse blocks and factors
+ *                 (FP32 accumulation for BF16).
+ *  coarse_matrix_free  0: assembled inherited coarse blocks (diagonal + 6 face
+ *                 neighbours, block-sparse);  1: coarse products applied as
+ *                 P^T K_0 P through the fine exact Jacobian action. */
+typedef struct {
+    int n_levels;
+    int p_level[4];
+    int nu_pre, nu_post;
+    double omega;
+    int coarsest_iters;
+    int prec_fine;
+    int prec_coarse;
+    int coarse_matrix_free;
+} pmg_opts;
+
+/* FGMRES(restart) (Sec. 6): x0 = 0, converged when the recomputed true
+ * residual ||b - K x|| <= rtol ||b||.  jvp_exact: 1 = tangent-linear Jacobian
+ * action as the Krylov operator, 0 = the finite-difference form of Eq. DG-mf. */
+typedef struct {
+    int restart, max_restarts;
+    double rtol;
+    int jvp_exact;
+} fgmres_opts;
+
+typedef struct {
+    int iters, restarts;
+    double rel_res_true, rel_res_est;
+} fgmres_stats;
+
+typedef struct {
+    int newton;              /* Newton iterations taken                        */
+    int linear_iters;        /* FGMRES iterations summed over Newton steps     */
+    double res0, res_final;  /* ||R_u(W_0)||, ||R_u(W_final)||                 */
+    double max_rel_res_true; /* worst true relative linear residual           */
+    double setup_seconds, solve_seconds;
+} dg_step_stats;
+
+/* Create a context for the periodic mesh, gas model and degree p (1..4) on the
+ * given HIP stream (hipStream_t; NULL = default stream) of the current device.
+ * Fails with DG_EINVAL on a bad mesh (non-positive Jacobian at a quadrature
+ * point, n < 1), bad p or gas constants. */
+dg_status dg_create(const dg_mesh_desc* mesh, const dg_phys* phys, int p, void* hip_stream, dg_ctx** out);
+dg_status dg_destroy(dg_ctx* ctx);
+size_t dg_ndof(const dg_ctx* ctx);                  /* ne * 5 * (p+1)^3 */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Physical coordinates of the (p+1)^3 volume Gauss points: xyz device
+ * [ne][(p+1)^3][3], points ordered (q1,q2,q3) with q3 fastest. */
+dg_status dg_quad_points(dg_ctx* ctx, double* xyz);
+
+/* L2 projection (with the volume Gauss rule) of point values given at the
+ * points of dg_quad_points: values device [ne][(p+1)^3][5] -> W. */
+dg_status dg_project(dg_ctx* ctx, const double* values, double* W);
+
+/* R = R(W): volume and face integrals of Sec. 3.1 Eq. dg_ns with the Roe flux
+ * and the BR2 viscous flux (Eqs. visc_flux, re). */
+dg_status dg_residual(dg_ctx* ctx, const double* W, double* R);
+
+/* y = shift * M v + (R(W + h v) - RW) / h, h = 1e-7 sqrt(1+||W||)/||v||
+ * (Sec. 5.1 Eq. DG-mf; step read as scaling with 1/||v||).  RW must be R(W).
+ * v = 0 gives y = 0. */
+dg_status dg_jvp(dg_ctx* ctx, const double* W, const double* RW, const double* v, double shift, double* y);
+
+/* y = shift * M v + (dR/dW)(W) v exactly (tangent-linear, forward mode). */
+dg_status dg_jvp_exact(dg_ctx* ctx, const double* W, const double* v, double shift, double* y);
+
+/* y = M v (block-diagonal mass matrix of Sec. 3.1). */
+dg_status dg_mass(dg_ctx* ctx, const double* v, double* y);
+
+/* Element diagonal blocks of K = shift M + dR/dW at W (Sec. 6.3), written to
+ * the caller's device buffer blocks [ne][nb][nb], nb = 5 (p+1)^3, each block
+ * COLUMN-major: blocks[e][j][i] = K[(e,i),(e,j)], local index
+ * i = equation * (p+1)^3 + mode. */
+dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* blocks);
+
+/* Batched PLU with partial pivoting (Sec. 6.3), in place, LAPACK convention
+ * (column-major blocks, rows k and piv[k] exchanged at step k, unit-lower L
+ * below the diagonal).  A device [nblk][n][n], piv device int [nblk][n].
+ * Enqueued on hip_stream.  A zero pivot is left in place (no error). */
+dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n);
+/* x = A^-1 b for every block with the factors of dg_batched_lu; b, x device [nblk][n]. */
+dg_status dg_batched_lu_solve(void* hip_stream, const double* LU, const int* piv, const double* b, double* x,
+                              int nblk, int n);
+
+/* Assemble and factor the p-multigrid preconditioner of K = shift M + dR/dW
+ * at W (Sec. 6, lagged: valid until the next pmg_setup). */
+dg_status pmg_setup(dg_ctx* ctx, const double* W, double shift, const pmg_opts* opts);
+
+/* z = one V-cycle of Alg. 2 applied to r from a zero initial guess
+ * (z ~ K^-1 r).  DG_ESTATE before pmg_setup. */
+dg_status pmg_apply(dg_ctx* ctx, const double* r, double* z);
+
+/* Solve K x = b by FGMRES with the current pmg preconditioner (identity if
+ * pmg_setup was never called); K is linearised at W with shift given by the
+ * last pmg_setup (or 0 without it).  RW must be R(W) (used by the FD
+ * operator).  x is overwritten (x0 = 0).  Synchronises the stream.
+ * DG_ENOCONV if max_restarts is exhausted (x holds the best iterate). */
+dg_status fgmres_step(dg_ctx* ctx, const double* W, const double* RW, const double* b, double* x,
+                      const fgmres_opts* opts, fgmres_stats* stats);
+
+/* One implicit BDF2 step (Sec. 4, Eq. NEWTON with BDF2 coefficients):
+ * Newton on R_u(W) = M(3W - 4Wn + Wnm1)/(2 dt) + R(W) from W_0 = Wn, linear
+ * systems (3/(2dt) M + dR/dW) x = -R_u by fgmres_step with the pMG
+ * preconditioner set up once at Wn (lagged over the step).  Stops when
+ * ||R_u|| <= newton_rtol ||R_u(W_0)|| or ||R_u|| <= 1e-14 (3/(2dt)) ||M Wn||,
+ * at most max_newton iterations (DG_ENOCONV after that).  Wnm1 == NULL means
+ * Wnm1 = Wn.  Wnp1 must not alias Wn or Wnm1. */
+dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
+                       const fgmres_opts* fopts, double newton_rtol, int max_newton, double* Wnp1,
+                       dg_step_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -164,7 +164,11 @@ class PMG:
     block projection M K M^T of Sec. 6.1 gives on the diagonal)."""
 
     def __init__(self, D, W, shift, levels, nu_pre=2, nu_post=2, omega=1.0, coarse_iters=30,
-                 RW=None, Dblk=None):
+                 RW=None, Dblk=None, coarse_op="exact"):
+        """coarse_op: "exact" applies P^T K_0 P with the exact Jacobian action
+        (the inherited operator of Sec. 6.1); "fd" applies P^T K_FD P with the
+        finite-difference product, a matrix-free approximation of it."""
+        self.coarse_op = coarse_op
         self.D, self.W, self.shift = D, W, shift
         self.RW = D.residual(W) if RW is None else RW
         self.levels = list(levels)
@@ -182,6 +186,8 @@ class PMG:
         if l == 0:
             return jvp_fd(D, self.W, self.RW, x, self.shift)
         xf = prolong(x, D.nv)
+        if self.coarse_op == "fd":
+            return restrict(jvp_fd(D, self.W, self.RW, xf, self.shift), self.levels[l])
         return restrict(jvp_exact(D, self.W, xf, self.shift), self.levels[l])
 
     def bj(self, l, r):
@@ -216,7 +222,7 @@ class PMG:
 
     def apply(self, r):
         if len(self.levels) == 1:
-            return self.smooth(0, None, r, max(1, self.nu_pre), True)
+            return self.bj(0, r)        # single grid: z = D^-1 r
         return self.vcycle(0, r)
 
 

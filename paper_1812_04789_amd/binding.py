@@ -1,0 +1,273 @@
+"""Thin ctypes binding of the C ABI in include/dg.h.
+
+Argument marshalling only: every step of the method runs in the HIP library
+libdg_mi355x.so.  PyTorch provides device memory (float64 CUDA tensors) and the
+HIP stream.  Importing this module does not need a GPU; creating a Context does,
+and fails loudly if the library is not built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdg_mi355x.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOCONV, DG_ENONFINITE, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
+STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
+          -5: "DG_ENONFINITE", -6: "DG_ESTATE"}
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("vtx", ctypes.POINTER(ctypes.c_double))]
+
+
+class Phys(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("eta", ctypes.c_double)]
+
+
+class PmgOpts(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("p_level", ctypes.c_int * 4), ("nu_pre", ctypes.c_int),
+                ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("coarsest_iters", ctypes.c_int),
+                ("prec_fine", ctypes.c_int), ("prec_coarse", ctypes.c_int), ("coarse_matrix_free", ctypes.c_int)]
+
+
+class FgmresOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_restarts", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("jvp_exact", ctypes.c_int)]
+
+
+class FgmresStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("newton", ctypes.c_int), ("linear_iters", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("max_rel_res_true", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
+
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+SIGNATURES = {
+    "dg_create": (_I, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Phys), _I, _P, ctypes.POINTER(_P)]),
+    "dg_destroy": (_I, [_P]),
+    "dg_ndof": (ctypes.c_size_t, [_P]),
+    "dg_last_error": (ctypes.c_char_p, [_P]),
+    "dg_quad_points": (_I, [_P, _P]),
+    "dg_project": (_I, [_P, _P, _P]),
+    "dg_residual": (_I, [_P, _P, _P]),
+    "dg_jvp": (_I, [_P, _P, _P, _P, _D, _P]),
+    "dg_jvp_exact": (_I, [_P, _P, _P, _D, _P]),
+    "dg_mass": (_I, [_P, _P, _P]),
+    "dg_assemble_diag": (_I, [_P, _P, _D, _P]),
+    "dg_batched_lu": (_I, [_P, _P, _P, _I, _I]),
+    "dg_batched_lu_solve": (_I, [_P, _P, _P, _P, _P, _I, _I]),
+    "pmg_setup": (_I, [_P, _P, _D, ctypes.POINTER(PmgOpts)]),
+    "pmg_apply": (_I, [_P, _P, _P]),
+    "fgmres_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(FgmresOpts), ctypes.POINTER(FgmresStats)]),
+    "dg_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
+                          ctypes.POINTER(StepStats)]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def pmg_opts(levels, nu_pre=2, nu_post=2, omega=1.0, coarsest_iters=30, prec_fine=DG_FP64,
+             prec_coarse=DG_FP64, coarse_matrix_free=1):
+    o = PmgOpts()
+    o.n_levels = len(levels)
+    for i, p in enumerate(levels):
+        o.p_level[i] = int(p)
+    o.nu_pre, o.nu_post, o.omega, o.coarsest_iters = nu_pre, nu_post, omega, coarsest_iters
+    o.prec_fine, o.prec_coarse, o.coarse_matrix_free = prec_fine, prec_coarse, coarse_matrix_free
+    return o
+
+
+def fgmres_opts(restart=30, rtol=1e-8, max_restarts=20, jvp_exact=1):
+    o = FgmresOpts()
+    o.restart, o.rtol, o.max_restarts, o.jvp_exact = restart, rtol, max_restarts, jvp_exact
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One DG discretisation on the current CUDA (HIP) device.
+
+    n: elements per direction; lo, hi: periodic box; p: degree (1..4);
+    gamma, mu (0 = Euler), Pr, eta: gas model and BR2 penalty;
+    vertices: optional host float64 array (ne, 8, 3) of Q1 vertices."""
+
+    def __init__(self, n, lo, hi, p, gamma=1.4, mu=0.0, Pr=0.72, eta=7.0, vertices=None, stream=None):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        md = MeshDesc()
+        md.nx, md.ny, md.nz = (int(x) for x in n)
+        for d in range(3):
+            md.lo[d] = float(lo[d])
+            md.hi[d] = float(hi[d])
+        self._vtx = None
+        if vertices is not None:
+            self._vtx = np.ascontiguousarray(vertices, dtype=np.float64)
+            md.vtx = self._vtx.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ph = Phys(gamma, mu, Pr, eta)
+        h = ctypes.c_void_p()
+        st = self.lib.dg_create(ctypes.byref(md), ctypes.byref(ph), int(p), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h))
+        if st != DG_OK:
+            raise DGError(st, "dg_create failed")
+        self.h = h
+        self.n, self.p = tuple(int(x) for x in n), int(p)
+        self.ne = md.nx * md.ny * md.nz
+        self.nv = (p + 1) ** 3
+        self.ndof = int(self.lib.dg_ndof(h))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    # ---- helpers -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != DG_OK:
+            raise DGError(st, self.lib.dg_last_error(self.h).decode())
+
+    def _vec(self, t, name, n=None):
+        torch = self.torch
+        n = self.ndof if n is None else n
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                and t.numel() == n):
+            raise ValueError("%s must be a contiguous float64 CUDA tensor with %d entries" % (name, n))
+        return _ptr(t)
+
+    def empty(self, n=None):
+        return self.torch.empty(self.ndof if n is None else n, dtype=self.torch.float64, device=self.device)
+
+    # ---- entry points ---------------------------------------------------------
+    def quad_points(self):
+        out = self.empty(self.ne * self.nv * 3)
+        self._check(self.lib.dg_quad_points(self.h, _ptr(out)))
+        return out.view(self.ne, self.nv, 3)
+
+    def project(self, values, W=None):
+        values = values.contiguous()
+        self._vec(values, "values", self.ne * self.nv * 5)
+        W = self.empty() if W is None else W
+        self._check(self.lib.dg_project(self.h, _ptr(values), self._vec(W, "W")))
+        return W
+
+    def residual(self, W, R=None):
+        R = self.empty() if R is None else R
+        self._check(self.lib.dg_residual(self.h, self._vec(W, "W"), self._vec(R, "R")))
+        return R
+
+    def jvp(self, W, RW, v, shift, y=None):
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_jvp(self.h, self._vec(W, "W"), self._vec(RW, "RW"), self._vec(v, "v"),
+                                    float(shift), self._vec(y, "y")))
+        return y
+
+    def jvp_exact(self, W, v, shift, y=None):
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_jvp_exact(self.h, self._vec(W, "W"), self._vec(v, "v"), float(shift),
+                                          self._vec(y, "y")))
+        return y
+
+    def mass(self, v, y=None):
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_mass(self.h, self._vec(v, "v"), self._vec(y, "y")))
+        return y
+
+    def assemble_diag(self, W, shift):
+        nb = 5 * self.nv
+        out = self.empty(self.ne * nb * nb)
+        self._check(self.lib.dg_assemble_diag(self.h, self._vec(W, "W"), float(shift), _ptr(out)))
+        return out.view(self.ne, nb, nb)       # [e][col][row]
+
+    def pmg_setup(self, W, shift, opts):
+        self._check(self.lib.pmg_setup(self.h, self._vec(W, "W"), float(shift), ctypes.byref(opts)))
+
+    def pmg_apply(self, r, z=None):
+        z = self.empty() if z is None else z
+        self._check(self.lib.pmg_apply(self.h, self._vec(r, "r"), self._vec(z, "z")))
+        return z
+
+    def fgmres(self, W, RW, b, opts, x=None, raise_on_noconv=True):
+        x = self.empty() if x is None else x
+        st = FgmresStats()
+        s = self.lib.fgmres_step(self.h, self._vec(W, "W"), self._vec(RW, "RW"), self._vec(b, "b"),
+                                 self._vec(x, "x"), ctypes.byref(opts), ctypes.byref(st))
+        if s != DG_OK and (raise_on_noconv or s != DG_ENOCONV):
+            self._check(s)
+        return x, st
+
+    def bdf2_step(self, Wn, Wnm1, dt, popts, fopts, newton_rtol=1e-10, max_newton=5, Wnp1=None):
+        Wnp1 = self.empty() if Wnp1 is None else Wnp1
+        st = StepStats()
+        wm = self._vec(Wnm1, "Wnm1") if Wnm1 is not None else None
+        self._check(self.lib.dg_bdf2_step(self.h, self._vec(Wn, "Wn"), wm, float(dt), ctypes.byref(popts),
+                                          ctypes.byref(fopts), float(newton_rtol), int(max_newton),
+                                          self._vec(Wnp1, "Wnp1"), ctypes.byref(st)))
+        return Wnp1, st
+
+
+def batched_lu(A, piv, stream=None):
+    """In-place PLU of a (nblk, n, n) float64 CUDA tensor holding column-major blocks."""
+    import torch
+    lib = load()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    nblk, n, _ = A.shape
+    st = lib.dg_batched_lu(ctypes.c_void_p(s.cuda_stream), _ptr(A), _ptr(piv), nblk, n)
+    if st != DG_OK:
+        raise DGError(st, "dg_batched_lu")
+
+
+def batched_lu_solve(LU, piv, b, x, stream=None):
+    import torch
+    lib = load()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    nblk, n, _ = LU.shape
+    st = lib.dg_batched_lu_solve(ctypes.c_void_p(s.cuda_stream), _ptr(LU), _ptr(piv), _ptr(b), _ptr(x), nblk, n)
+    if st != DG_OK:
+        raise DGError(st, "dg_batched_lu_solve")

@@ -1,0 +1,746 @@
+// C ABI of the MI355X DG hot path (include/dg.h) and the host-side
+// orchestration of the device kernels: p-multigrid V-cycle (Sec. 6, Alg. 2),
+// block-Jacobi smoothing (Sec. 6.3), right-preconditioned GMRES on the
+// coarsest level and flexible GMRES outside (Sec. 6), BDF2 + Newton
+// (Sec. 4, Eq. NEWTON).  Every arithmetic step runs in a device kernel; the
+// host only sequences launches and, in FGMRES and Newton, reads one scalar per
+// iteration to test convergence.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace dg;
+
+namespace dg {
+hipError_t launch_givens(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est, hipStream_t s);
+hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s);
+hipError_t launch_gs_finish(double* hcol, const double* h2, int jp1, const double* nrm2, double* nrm, hipStream_t s);
+hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s);
+}  // namespace dg
+
+namespace {
+
+struct DgError {
+    dg_status st;
+};
+
+// Device buffer owned by the context.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void ensure(size_t want) {
+        if (want <= n) return;
+        release();
+        if (hipMalloc(&p, want * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            n = 0;
+            throw DgError{DG_ENOMEM};
+        }
+        n = want;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// Krylov workspace (Arnoldi basis, preconditioned directions, Hessenberg).
+struct Krylov {
+    int m = 0;
+    size_t N = 0;
+    DBuf<double> V, Z, H, cs, sn, g, y, h2, sc;
+    void ensure(int m_, size_t N_) {
+        m = m_;
+        N = N_;
+        V.ensure((size_t)(m + 1) * N);
+        Z.ensure((size_t)m * N);
+        H.ensure((size_t)(m + 1) * m);
+        cs.ensure(m);
+        sn.ensure(m);
+        g.ensure(m + 1);
+        y.ensure(m);
+        h2.ensure(m + 1);
+        sc.ensure(8);
+    }
+    void release() {
+        V.release(); Z.release(); H.release(); cs.release(); sn.release(); g.release(); y.release();
+        h2.release(); sc.release();
+    }
+};
+
+struct Level {
+    int p = 0, nv = 0, nb = 0;
+    size_t ndof = 0;
+    DBuf<double> f64;     // factors (FP64)
+    DBuf<float> f32;      // factors (FP32)
+    DBuf<int> piv;
+    bool use32 = false;
+    DBuf<double> x, b, r, t, z;
+    void release() { f64.release(); f32.release(); piv.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
+};
+
+std::mutex g_tab_mu;
+bool g_tab_built = false;
+Tab g_tabs[MAXP + 1];
+short g_perm[PERM_TOTAL];
+bool g_tab_uploaded[64] = {false};
+
+}  // namespace
+
+struct dg_ctx {
+    int device = 0;
+    hipStream_t s = nullptr;
+    DGArgs a{};
+    int p = 0, nv = 0, nb = 0, ne = 0;
+    size_t N = 0;
+    std::string err;
+    DBuf<double> vtx;                       // Q1 vertices of every element (also for straight boxes)
+    DBuf<double> partial, scal;
+    DBuf<int> flag;
+    DBuf<double> tmp1, tmp2, tmp3;          // N-vector scratch for jvp / pMG / Newton
+    // preconditioner
+    bool pmg_ready = false;
+    pmg_opts popt{};
+    double shift = 0.0;
+    DBuf<double> W0, RW0, blk;
+    std::vector<Level> lv;
+    Krylov kc;                              // coarsest-level GMRES
+    Krylov kf;                              // outer FGMRES
+    // Newton
+    DBuf<double> RW, Ru, xN;
+};
+
+namespace {
+
+// scalar slots in ctx->scal
+enum { S_NW2 = 0, S_NV2 = 1, S_H = 2, S_TMP = 3, S_PMG_NW2 = 8, S_F_NW2 = 9, S_F_EST = 10, S_F_B2 = 11,
+       S_F_R2 = 12, S_N_R2 = 13, S_N_M2 = 14, S_C0 = 16, S_COUNT = 32 };
+
+#define CK(expr)                                                                          \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            throw DgError{DG_EHIP};                                                       \
+        }                                                                                 \
+    } while (0)
+
+void fail(dg_ctx* ctx, dg_status st, const std::string& msg) {
+    ctx->err = msg;
+    throw DgError{st};
+}
+
+double* sc(dg_ctx* ctx, int slot) { return ctx->scal.p + slot; }
+
+double read_scalar(dg_ctx* ctx, const double* dptr) {
+    double v = 0.0;
+    CK(hipMemcpyAsync(&v, dptr, sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    CK(hipStreamSynchronize(ctx->s));
+    return v;
+}
+
+void dot(dg_ctx* ctx, const double* x, const double* y, size_t n, double* out) {
+    CK(launch_dot(x, y, n, ctx->partial.p, out, ctx->s));
+}
+
+// y = shift M v + (R(W + h v) - RW)/h.  nw2: device ||W||^2 (computed if null).
+void jvp_fd(dg_ctx* ctx, const double* W, const double* RW, const double* v, double shift, double* y,
+            const double* nw2) {
+    if (!nw2) {
+        dot(ctx, W, W, ctx->N, sc(ctx, S_NW2));
+        nw2 = sc(ctx, S_NW2);
+    }
+    dot(ctx, v, v, ctx->N, sc(ctx, S_NV2));
+    CK(launch_fd_step(nw2, sc(ctx, S_NV2), 1e-7, sc(ctx, S_H), ctx->s));
+    CK(launch_jvp_fd(ctx->a, W, RW, v, sc(ctx, S_H), shift, y, ctx->s));
+}
+
+// ---- p-multigrid ------------------------------------------------------------------
+void bj_apply(dg_ctx* ctx, int l, const double* r, double* z) {
+    Level& L = ctx->lv[l];
+    if (L.use32) CK(launch_lu_solve<float>(L.f32.p, L.piv.p, r, z, ctx->ne, L.nb, ctx->s));
+    else CK(launch_lu_solve<double>(L.f64.p, L.piv.p, r, z, ctx->ne, L.nb, ctx->s));
+}
+
+// y = K_l x (level operator): level 0 the FD product (Eq. DG-mf) at the
+// lagged state; coarse levels the inherited P^T K_0 P applied matrix-free.
+void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
+    if (l == 0) {
+        jvp_fd(ctx, ctx->W0.p, ctx->RW0.p, x, ctx->shift, y, sc(ctx, S_PMG_NW2));
+        return;
+    }
+    const Level& L = ctx->lv[l];
+    CK(launch_prolong_add(ctx->ne, ctx->nv, L.nv, x, ctx->tmp1.p, 1, ctx->s));
+    jvp_fd(ctx, ctx->W0.p, ctx->RW0.p, ctx->tmp1.p, ctx->shift, ctx->tmp2.p, sc(ctx, S_PMG_NW2));
+    CK(launch_restrict(ctx->ne, ctx->nv, L.nv, ctx->tmp2.p, y, ctx->s));
+}
+
+void smooth(dg_ctx* ctx, int l, double* x, const double* b, int nu, bool x_zero) {
+    Level& L = ctx->lv[l];
+    const double om = ctx->popt.omega;
+    for (int s = 0; s < nu; ++s) {
+        if (s == 0 && x_zero) {
+            bj_apply(ctx, l, b, L.z.p);
+            CK(launch_axpby(L.ndof, om, L.z.p, 0.0, nullptr, x, ctx->s));
+        } else {
+            level_op(ctx, l, x, L.t.p);
+            CK(launch_axpby(L.ndof, 1.0, b, -1.0, L.t.p, L.r.p, ctx->s));
+            bj_apply(ctx, l, L.r.p, L.z.p);
+            CK(launch_axpby(L.ndof, om, L.z.p, 1.0, x, x, ctx->s));
+        }
+    }
+    if (nu == 0 && x_zero) CK(launch_fill(L.ndof, 0.0, x, ctx->s));
+}
+
+// Arnoldi step j with classical Gram-Schmidt applied twice; w is in V[j+1].
+void arnoldi_orth(dg_ctx* ctx, Krylov& K, int j, size_t n) {
+    double* w = K.V.p + (size_t)(j + 1) * n;
+    double* hcol = K.H.p + (size_t)j * (K.m + 1);
+    CK(launch_multi_dot(K.V.p, n, j + 1, w, n, ctx->partial.p, hcol, ctx->s));
+    CK(launch_multi_axpy(n, j + 1, hcol, -1, K.V.p, n, w, ctx->s));
+    CK(launch_multi_dot(K.V.p, n, j + 1, w, n, ctx->partial.p, K.h2.p, ctx->s));
+    CK(launch_multi_axpy(n, j + 1, K.h2.p, -1, K.V.p, n, w, ctx->s));
+    dot(ctx, w, w, n, K.sc.p + 0);
+    CK(launch_gs_finish(hcol, K.h2.p, j + 1, K.sc.p + 0, K.sc.p + 1, ctx->s));
+    CK(launch_scale_dev(n, w, K.sc.p + 1, 1, w, ctx->s));
+    CK(launch_givens(K.H.p, K.m + 1, j, K.cs.p, K.sn.p, K.g.p, K.sc.p + 2, ctx->s));
+}
+
+// Coarsest SOLVE: right-preconditioned GMRES(BJ) from x = 0 for exactly
+// `iters` steps, all on the device (no host synchronisation).
+void coarse_gmres(dg_ctx* ctx, int l, const double* b, double* x, int iters) {
+    Level& L = ctx->lv[l];
+    Krylov& K = ctx->kc;
+    const size_t n = L.ndof;
+    dot(ctx, b, b, n, K.sc.p + 3);
+    CK(launch_init_g(K.g.p, iters + 1, K.sc.p + 3, ctx->s));
+    CK(launch_scale_dev(n, b, K.g.p, 1, K.V.p, ctx->s));
+    for (int j = 0; j < iters; ++j) {
+        double* z = K.Z.p + (size_t)j * n;
+        bj_apply(ctx, l, K.V.p + (size_t)j * n, z);
+        level_op(ctx, l, z, K.V.p + (size_t)(j + 1) * n);
+        arnoldi_orth(ctx, K, j, n);
+    }
+    CK(launch_backsolve(K.H.p, K.m + 1, iters, K.g.p, K.y.p, ctx->s));
+    CK(launch_fill(n, 0.0, x, ctx->s));
+    CK(launch_multi_axpy(n, iters, K.y.p, 1, K.Z.p, n, x, ctx->s));
+}
+
+// Alg. 2: MG_V(l, b_l, x_l = 0)
+void vcycle(dg_ctx* ctx, int l, const double* b, double* x) {
+    const int Lc = (int)ctx->lv.size() - 1;
+    if (l == Lc) {
+        coarse_gmres(ctx, l, b, x, ctx->popt.coarsest_iters);
+        return;
+    }
+    Level& L = ctx->lv[l];
+    Level& C = ctx->lv[l + 1];
+    smooth(ctx, l, x, b, ctx->popt.nu_pre, true);
+    level_op(ctx, l, x, L.t.p);
+    CK(launch_axpby(L.ndof, 1.0, b, -1.0, L.t.p, L.r.p, ctx->s));
+    CK(launch_restrict(ctx->ne, L.nv, C.nv, L.r.p, C.b.p, ctx->s));
+    vcycle(ctx, l + 1, C.b.p, C.x.p);
+    CK(launch_prolong_add(ctx->ne, L.nv, C.nv, C.x.p, x, 0, ctx->s));
+    smooth(ctx, l, x, b, ctx->popt.nu_post, false);
+}
+
+void pmg_apply_impl(dg_ctx* ctx, const double* r, double* z) {
+    if (!ctx->pmg_ready) fail(ctx, DG_ESTATE, "pmg_apply before pmg_setup");
+    if (ctx->lv.size() == 1) {
+        bj_apply(ctx, 0, r, z);
+        return;
+    }
+    vcycle(ctx, 0, r, z);
+}
+
+void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
+    if (!o) fail(ctx, DG_EINVAL, "null pmg_opts");
+    if (o->n_levels < 1 || o->n_levels > 4) fail(ctx, DG_EINVAL, "n_levels must be 1..4");
+    if (o->p_level[0] != ctx->p) fail(ctx, DG_EINVAL, "p_level[0] must equal the context degree");
+    for (int l = 1; l < o->n_levels; ++l)
+        if (o->p_level[l] < 1 || o->p_level[l] >= o->p_level[l - 1])
+            fail(ctx, DG_EINVAL, "coarse degrees must decrease and be >= 1");
+    if (o->nu_pre < 0 || o->nu_post < 0 || o->coarsest_iters < 1 || o->coarsest_iters > 200)
+        fail(ctx, DG_EINVAL, "bad sweep or coarsest iteration counts");
+    if (o->prec_fine != DG_FP64 && o->prec_fine != DG_FP32) fail(ctx, DG_EINVAL, "prec_fine must be FP64 or FP32");
+    if (o->prec_coarse != DG_FP64 && o->prec_coarse != DG_FP32)
+        fail(ctx, DG_EINVAL, "prec_coarse must be FP64 or FP32");
+    if (!o->coarse_matrix_free && o->n_levels > 1)
+        fail(ctx, DG_EINVAL, "assembled coarse operators are not available in this build");
+}
+
+void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* o) {
+    check_pmg_opts(ctx, o);
+    ctx->pmg_ready = false;
+    ctx->popt = *o;
+    ctx->shift = shift;
+    const size_t N = ctx->N;
+    ctx->W0.ensure(N);
+    ctx->RW0.ensure(N);
+    CK(launch_copy(N, W, ctx->W0.p, ctx->s));
+    CK(launch_residual(ctx->a, ctx->W0.p, ctx->RW0.p, ctx->s));
+    dot(ctx, ctx->W0.p, ctx->W0.p, N, sc(ctx, S_PMG_NW2));
+    const int nb = ctx->nb;
+    ctx->blk.ensure((size_t)ctx->ne * nb * nb);
+    CK(launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->s));
+    for (size_t l = o->n_levels; l < ctx->lv.size(); ++l) ctx->lv[l].release();
+    ctx->lv.resize(o->n_levels);
+    for (int l = 0; l < o->n_levels; ++l) {
+        Level& L = ctx->lv[l];
+        L.p = o->p_level[l];
+        L.nv = (L.p + 1) * (L.p + 1) * (L.p + 1);
+        L.nb = 5 * L.nv;
+        L.ndof = (size_t)ctx->ne * L.nb;
+        L.use32 = (l == 0) ? (o->prec_fine == DG_FP32) : (o->prec_coarse == DG_FP32);
+        L.piv.ensure((size_t)ctx->ne * L.nb);
+        L.x.ensure(L.ndof);
+        L.b.ensure(L.ndof);
+        L.r.ensure(L.ndof);
+        L.t.ensure(L.ndof);
+        L.z.ensure(L.ndof);
+    }
+    // coarse blocks are principal sub-blocks of the unfactored fine blocks
+    for (int l = o->n_levels - 1; l >= 0; --l) {
+        Level& L = ctx->lv[l];
+        const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
+        if (L.use32) {
+            L.f32.ensure(sz);
+            if (l == 0) CK(launch_convert_fp64_to_fp32(ctx->blk.p, L.f32.p, sz, ctx->s));
+            else CK(launch_extract_sub<float>(ctx->blk.p, nb, ctx->nv, L.nv, L.f32.p, ctx->ne, ctx->s));
+            CK(launch_lu<float>(L.f32.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+        } else {
+            if (l == 0) {
+                CK(launch_lu<double>(ctx->blk.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+            } else {
+                L.f64.ensure(sz);
+                CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, L.f64.p, ctx->ne, ctx->s));
+                CK(launch_lu<double>(L.f64.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+            }
+        }
+    }
+    // level 0 FP64 factors live in blk (factored in place)
+    if (!ctx->lv[0].use32) {
+        std::swap(ctx->lv[0].f64.p, ctx->blk.p);
+        std::swap(ctx->lv[0].f64.n, ctx->blk.n);
+    }
+    if (o->n_levels > 1) {
+        const Level& Lc = ctx->lv.back();
+        ctx->kc.ensure(o->coarsest_iters, Lc.ndof);
+    }
+    ctx->pmg_ready = true;
+}
+
+// ---- FGMRES (Sec. 6) --------------------------------------------------------------------
+void fgmres_impl(dg_ctx* ctx, const double* W, const double* RW, const double* b, double* x, const fgmres_opts* o,
+                 fgmres_stats* st) {
+    if (!o || o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->rtol > 0.0))
+        fail(ctx, DG_EINVAL, "bad fgmres_opts");
+    const size_t n = ctx->N;
+    Krylov& K = ctx->kf;
+    const int m = o->restart;
+    K.ensure(m, n);
+    fgmres_stats loc{};
+    const double shift = ctx->pmg_ready ? ctx->shift : 0.0;
+    auto op = [&](const double* v, double* y) {
+        if (o->jvp_exact) CK(launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s));
+        else jvp_fd(ctx, W, RW, v, shift, y, sc(ctx, S_F_NW2));
+    };
+    if (!o->jvp_exact) dot(ctx, W, W, n, sc(ctx, S_F_NW2));
+    dot(ctx, b, b, n, sc(ctx, S_F_B2));
+    const double bn = std::sqrt(read_scalar(ctx, sc(ctx, S_F_B2)));
+    CK(launch_fill(n, 0.0, x, ctx->s));
+    if (!std::isfinite(bn)) fail(ctx, DG_ENONFINITE, "non-finite right-hand side");
+    if (bn == 0.0) {
+        loc.rel_res_true = loc.rel_res_est = 0.0;
+        if (st) *st = loc;
+        return;
+    }
+    double* r = ctx->tmp3.p;
+    CK(launch_copy(n, b, r, ctx->s));
+    double beta = bn;
+    bool converged = false;
+    for (int rs = 0; rs <= o->max_restarts; ++rs) {
+        if (rs > 0) {
+            dot(ctx, r, r, n, sc(ctx, S_F_R2));
+        } else {
+            CK(launch_copy(1, sc(ctx, S_F_B2), sc(ctx, S_F_R2), ctx->s));
+        }
+        CK(launch_init_g(K.g.p, m + 1, sc(ctx, S_F_R2), ctx->s));
+        CK(launch_scale_dev(n, r, K.g.p, 1, K.V.p, ctx->s));
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double* z = K.Z.p + (size_t)j * n;
+            if (ctx->pmg_ready) pmg_apply_impl(ctx, K.V.p + (size_t)j * n, z);
+            else CK(launch_copy(n, K.V.p + (size_t)j * n, z, ctx->s));
+            op(z, K.V.p + (size_t)(j + 1) * n);
+            arnoldi_orth(ctx, K, j, n);
+            k = j + 1;
+            loc.iters++;
+            const double est = read_scalar(ctx, K.sc.p + 2);
+            if (!std::isfinite(est)) fail(ctx, DG_ENONFINITE, "non-finite Krylov residual estimate");
+            loc.rel_res_est = est / bn;
+            if (est <= o->rtol * bn) break;
+        }
+        CK(launch_backsolve(K.H.p, m + 1, k, K.g.p, K.y.p, ctx->s));
+        CK(launch_multi_axpy(n, k, K.y.p, 1, K.Z.p, n, x, ctx->s));
+        // true residual
+        op(x, ctx->tmp2.p);
+        CK(launch_axpby(n, 1.0, b, -1.0, ctx->tmp2.p, r, ctx->s));
+        dot(ctx, r, r, n, sc(ctx, S_F_R2));
+        beta = std::sqrt(read_scalar(ctx, sc(ctx, S_F_R2)));
+        loc.rel_res_true = beta / bn;
+        if (!std::isfinite(beta)) fail(ctx, DG_ENONFINITE, "non-finite true residual");
+        if (beta <= o->rtol * bn) {
+            converged = true;
+            break;
+        }
+        if (rs < o->max_restarts) loc.restarts++;
+    }
+    if (st) *st = loc;
+    if (!converged) fail(ctx, DG_ENOCONV, "FGMRES did not reach rtol");
+}
+
+void ensure_scratch(dg_ctx* ctx) {
+    ctx->tmp1.ensure(ctx->N);
+    ctx->tmp2.ensure(ctx->N);
+    ctx->tmp3.ensure(ctx->N);
+}
+
+void bdf2_impl(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* po,
+               const fgmres_opts* fo, double rtol, int max_newton, double* Wnp1, dg_step_stats* st) {
+    if (!(dt > 0.0) || !(rtol > 0.0) || max_newton < 1) fail(ctx, DG_EINVAL, "bad dt / newton_rtol / max_newton");
+    const size_t n = ctx->N;
+    const double a = 1.5 / dt;
+    if (!Wnm1) Wnm1 = Wn;
+    dg_step_stats loc{};
+    ctx->RW.ensure(n);
+    ctx->Ru.ensure(n);
+    ctx->xN.ensure(n);
+    double* W = Wnp1;
+    CK(launch_copy(n, Wn, W, ctx->s));
+    CK(hipStreamSynchronize(ctx->s));
+    auto t0 = std::chrono::steady_clock::now();
+    pmg_setup_impl(ctx, Wn, a, po);
+    CK(hipStreamSynchronize(ctx->s));
+    auto t1 = std::chrono::steady_clock::now();
+    // ||M Wn|| for the rounding floor
+    CK(launch_mass(ctx->a, Wn, ctx->tmp1.p, 1.0, 0, ctx->s));
+    dot(ctx, ctx->tmp1.p, ctx->tmp1.p, n, sc(ctx, S_N_M2));
+    const double floor = 1e-14 * a * std::sqrt(read_scalar(ctx, sc(ctx, S_N_M2)));
+    auto unsteady = [&]() -> double {
+        CK(launch_residual(ctx->a, W, ctx->RW.p, ctx->s));
+        // t = 3 W - 4 Wn + Wnm1 ; Ru = M t / (2 dt) + RW
+        CK(launch_axpby(n, 3.0, W, -4.0, Wn, ctx->tmp1.p, ctx->s));
+        CK(launch_axpby(n, 1.0, Wnm1, 1.0, ctx->tmp1.p, ctx->tmp1.p, ctx->s));
+        CK(launch_copy(n, ctx->RW.p, ctx->Ru.p, ctx->s));
+        CK(launch_mass(ctx->a, ctx->tmp1.p, ctx->Ru.p, 0.5 / dt, 1, ctx->s));
+        dot(ctx, ctx->Ru.p, ctx->Ru.p, n, sc(ctx, S_N_R2));
+        return std::sqrt(read_scalar(ctx, sc(ctx, S_N_R2)));
+    };
+    double r = unsteady();
+    if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
+    loc.res0 = r;
+    double worst = 0.0;
+    bool conv = false;
+    for (int k = 0; k < max_newton; ++k) {
+        if (r <= rtol * loc.res0 || r <= floor) {
+            conv = true;
+            break;
+        }
+        CK(launch_axpby(n, -1.0, ctx->Ru.p, 0.0, nullptr, ctx->tmp3.p, ctx->s));   // b = -R_u
+        // fgmres uses tmp2/tmp3 internally: keep b in Ru (negated in place)
+        CK(launch_copy(n, ctx->tmp3.p, ctx->Ru.p, ctx->s));
+        fgmres_stats fs{};
+        fgmres_impl(ctx, W, ctx->RW.p, ctx->Ru.p, ctx->xN.p, fo, &fs);
+        loc.linear_iters += fs.iters;
+        if (fs.rel_res_true > worst) worst = fs.rel_res_true;
+        CK(launch_axpby(n, 1.0, ctx->xN.p, 1.0, W, W, ctx->s));
+        loc.newton++;
+        r = unsteady();
+        if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
+    }
+    if (!conv && (r <= rtol * loc.res0 || r <= floor)) conv = true;
+    CK(hipStreamSynchronize(ctx->s));
+    auto t2 = std::chrono::steady_clock::now();
+    loc.res_final = r;
+    loc.max_rel_res_true = worst;
+    loc.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
+    loc.solve_seconds = std::chrono::duration<double>(t2 - t1).count();
+    if (st) *st = loc;
+    if (!conv) fail(ctx, DG_ENOCONV, "Newton did not converge");
+}
+
+template <class F>
+dg_status guarded(dg_ctx* ctx, F&& f) {
+    if (!ctx) return DG_EINVAL;
+    try {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
+        f();
+        ctx->err.clear();
+        return DG_OK;
+    } catch (const DgError& e) {
+        if (ctx->err.empty()) ctx->err = "error";
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return DG_ENOMEM;
+    } catch (...) {
+        ctx->err = "unexpected exception";
+        return DG_EINVAL;
+    }
+}
+
+void need(dg_ctx* ctx, const void* p, const char* what) {
+    if (!p) fail(ctx, DG_EINVAL, std::string("null pointer: ") + what);
+}
+void no_alias(dg_ctx* ctx, const void* out, const void* in, const char* what) {
+    if (out && in && out == in) fail(ctx, DG_EINVAL, std::string("output aliases input: ") + what);
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+dg_status dg_create(const dg_mesh_desc* mesh, const dg_phys* phys, int p, void* hip_stream, dg_ctx** out) {
+    if (!out) return DG_EINVAL;
+    *out = nullptr;
+    if (!mesh || !phys) return DG_EINVAL;
+    if (p < 1 || p > MAXP) return DG_EINVAL;
+    if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return DG_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!(mesh->hi[d] > mesh->lo[d])) return DG_EINVAL;
+    if (!(phys->gamma > 1.0) || phys->mu < 0.0 || (phys->mu > 0.0 && !(phys->Pr > 0.0)) || phys->eta < 0.0)
+        return DG_EINVAL;
+    const long long ne_ll = (long long)mesh->nx * mesh->ny * mesh->nz;
+    if (ne_ll > (1ll << 30)) return DG_EINVAL;
+    dg_ctx* ctx = new (std::nothrow) dg_ctx();
+    if (!ctx) return DG_ENOMEM;
+    dg_status st = DG_OK;
+    try {
+        CK(hipGetDevice(&ctx->device));
+        {
+            std::lock_guard<std::mutex> lk(g_tab_mu);
+            if (!g_tab_built) {
+                build_tables(g_tabs, g_perm);
+                g_tab_built = true;
+            }
+            if (ctx->device < 0 || ctx->device >= 64) fail(ctx, DG_EINVAL, "device index out of range");
+            if (!g_tab_uploaded[ctx->device]) {
+                CK(upload_tables(g_tabs, g_perm));
+                g_tab_uploaded[ctx->device] = true;
+            }
+        }
+        ctx->s = (hipStream_t)hip_stream;
+        ctx->p = p;
+        ctx->nv = (p + 1) * (p + 1) * (p + 1);
+        ctx->nb = 5 * ctx->nv;
+        ctx->ne = (int)ne_ll;
+        ctx->N = (size_t)ctx->ne * ctx->nb;
+        MeshDev& m = ctx->a.m;
+        m.nx = mesh->nx;
+        m.ny = mesh->ny;
+        m.nz = mesh->nz;
+        m.ne = ctx->ne;
+        for (int d = 0; d < 3; ++d) m.h[d] = (mesh->hi[d] - mesh->lo[d]) / (&mesh->nx)[d];
+        m.vtx = nullptr;
+        ctx->a.g = Gas{phys->gamma, phys->mu, phys->Pr, phys->eta};
+        ctx->a.p = p;
+        ctx->a.ns = phys->mu > 0.0;
+        ctx->partial.ensure((size_t)RED_BLOCKS * 256);
+        ctx->scal.ensure(S_COUNT);
+        ctx->flag.ensure(4);
+        ensure_scratch(ctx);
+        std::vector<double> hv;
+        const double* src = mesh->vtx;
+        if (!src) {      // straight box vertices (used for the quadrature point coordinates only)
+            hv.resize((size_t)ctx->ne * 24);
+            for (int k = 0; k < m.nz; ++k)
+                for (int j = 0; j < m.ny; ++j)
+                    for (int i = 0; i < m.nx; ++i) {
+                        const size_t e = (size_t)i + (size_t)m.nx * (j + (size_t)m.ny * k);
+                        for (int v = 0; v < 8; ++v) {
+                            const int c[3] = {i + (v & 1), j + ((v >> 1) & 1), k + ((v >> 2) & 1)};
+                            for (int d = 0; d < 3; ++d) hv[e * 24 + v * 3 + d] = mesh->lo[d] + m.h[d] * c[d];
+                        }
+                    }
+            src = hv.data();
+        }
+        ctx->vtx.ensure((size_t)ctx->ne * 24);
+        CK(hipMemcpyAsync(ctx->vtx.p, src, (size_t)ctx->ne * 24 * sizeof(double), hipMemcpyHostToDevice, ctx->s));
+        CK(hipStreamSynchronize(ctx->s));
+        if (mesh->vtx) {
+            m.vtx = ctx->vtx.p;
+            CK(hipMemsetAsync(ctx->flag.p, 0, sizeof(int), ctx->s));
+            CK(launch_check_jacobian(ctx->a, ctx->flag.p, ctx->s));
+            int bad = 0;
+            CK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->s));
+            CK(hipStreamSynchronize(ctx->s));
+            if (bad) fail(ctx, DG_EINVAL, "non-positive Jacobian determinant at a quadrature point");
+        }
+    } catch (const DgError& e) {
+        st = e.st;
+    } catch (...) {
+        st = DG_ENOMEM;
+    }
+    if (st != DG_OK) {
+        dg_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return DG_OK;
+}
+
+dg_status dg_destroy(dg_ctx* ctx) {
+    if (!ctx) return DG_EINVAL;
+    if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+    else (void)hipDeviceSynchronize();
+    ctx->vtx.release(); ctx->partial.release(); ctx->scal.release(); ctx->flag.release();
+    ctx->tmp1.release(); ctx->tmp2.release(); ctx->tmp3.release();
+    ctx->W0.release(); ctx->RW0.release(); ctx->blk.release();
+    for (auto& L : ctx->lv) L.release();
+    ctx->kc.release(); ctx->kf.release();
+    ctx->RW.release(); ctx->Ru.release(); ctx->xN.release();
+    delete ctx;
+    return DG_OK;
+}
+
+size_t dg_ndof(const dg_ctx* ctx) { return ctx ? ctx->N : 0; }
+
+const char* dg_last_error(const dg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+dg_status dg_quad_points(dg_ctx* ctx, double* xyz) {
+    return guarded(ctx, [&] {
+        need(ctx, xyz, "xyz");
+        DGArgs a = ctx->a;
+        a.m.vtx = ctx->vtx.p;
+        CK(launch_quad_points(a, xyz, ctx->s));
+    });
+}
+
+dg_status dg_project(dg_ctx* ctx, const double* values, double* W) {
+    return guarded(ctx, [&] {
+        need(ctx, values, "values");
+        need(ctx, W, "W");
+        no_alias(ctx, W, values, "W/values");
+        CK(launch_project(ctx->a, values, W, ctx->s));
+    });
+}
+
+dg_status dg_residual(dg_ctx* ctx, const double* W, double* R) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, R, "R");
+        no_alias(ctx, R, W, "R/W");
+        CK(launch_residual(ctx->a, W, R, ctx->s));
+    });
+}
+
+dg_status dg_jvp(dg_ctx* ctx, const double* W, const double* RW, const double* v, double shift, double* y) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, RW, "RW");
+        need(ctx, v, "v");
+        need(ctx, y, "y");
+        no_alias(ctx, y, W, "y/W");
+        no_alias(ctx, y, v, "y/v");
+        no_alias(ctx, y, RW, "y/RW");
+        jvp_fd(ctx, W, RW, v, shift, y, nullptr);
+    });
+}
+
+dg_status dg_jvp_exact(dg_ctx* ctx, const double* W, const double* v, double shift, double* y) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, v, "v");
+        need(ctx, y, "y");
+        no_alias(ctx, y, W, "y/W");
+        no_alias(ctx, y, v, "y/v");
+        CK(launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s));
+    });
+}
+
+dg_status dg_mass(dg_ctx* ctx, const double* v, double* y) {
+    return guarded(ctx, [&] {
+        need(ctx, v, "v");
+        need(ctx, y, "y");
+        no_alias(ctx, y, v, "y/v");
+        CK(launch_mass(ctx->a, v, y, 1.0, 0, ctx->s));
+    });
+}
+
+dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* blocks) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, blocks, "blocks");
+        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->s));
+    });
+}
+
+dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n) {
+    if (!A || !piv || nblk < 0 || n < 1 || n > 4096) return DG_EINVAL;
+    if (launch_lu<double>(A, piv, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
+    return DG_OK;
+}
+
+dg_status dg_batched_lu_solve(void* hip_stream, const double* LU, const int* piv, const double* b, double* x,
+                              int nblk, int n) {
+    if (!LU || !piv || !b || !x || b == x || nblk < 0 || n < 1 || n > 4096) return DG_EINVAL;
+    if (launch_lu_solve<double>(LU, piv, b, x, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
+    return DG_OK;
+}
+
+dg_status pmg_setup(dg_ctx* ctx, const double* W, double shift, const pmg_opts* opts) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        pmg_setup_impl(ctx, W, shift, opts);
+    });
+}
+
+dg_status pmg_apply(dg_ctx* ctx, const double* r, double* z) {
+    return guarded(ctx, [&] {
+        need(ctx, r, "r");
+        need(ctx, z, "z");
+        no_alias(ctx, z, r, "z/r");
+        pmg_apply_impl(ctx, r, z);
+    });
+}
+
+dg_status fgmres_step(dg_ctx* ctx, const double* W, const double* RW, const double* b, double* x,
+                      const fgmres_opts* opts, fgmres_stats* stats) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, b, "b");
+        need(ctx, x, "x");
+        if (!opts || !opts->jvp_exact) need(ctx, RW, "RW");
+        no_alias(ctx, x, b, "x/b");
+        no_alias(ctx, x, W, "x/W");
+        fgmres_impl(ctx, W, RW, b, x, opts, stats);
+    });
+}
+
+dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
+                       const fgmres_opts* fopts, double newton_rtol, int max_newton, double* Wnp1,
+                       dg_step_stats* stats) {
+    return guarded(ctx, [&] {
+        need(ctx, Wn, "Wn");
+        need(ctx, Wnp1, "Wnp1");
+        no_alias(ctx, Wnp1, Wn, "Wnp1/Wn");
+        no_alias(ctx, Wnp1, Wnm1, "Wnp1/Wnm1");
+        bdf2_impl(ctx, Wn, Wnm1, dt, popts, fopts, newton_rtol, max_newton, Wnp1, stats);
+    });
+}
+
+}  // extern "C"

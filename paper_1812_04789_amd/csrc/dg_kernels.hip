@@ -1,0 +1,829 @@
+// Fused DG kernels for gfx950: residual R(W) (Sec. 3.1, Eq. dg_ns with the
+// Roe flux and BR2, Eqs. visc_flux and re), the matrix-free product of
+// Sec. 5.1 (Eq. DG-mf), its exact forward-mode counterpart, and the columns
+// of the element diagonal blocks of K = a M + dR/dW (Sec. 6.3).
+//
+// Design (one kernel per call, no intermediate HBM traffic):
+//  * one element per (p+1)^3 work-items; every work-item owns one volume
+//    Gauss point; elements are packed so a workgroup is one or two wavefronts;
+//  * sum-factorised interpolation modal -> Gauss values (three 1D sweeps
+//    through LDS), reference gradients by the collocation derivative;
+//  * each element evaluates all six of its faces: its own traces from its
+//    Gauss values (Lagrange weights of the end points), the neighbour's
+//    traces from the neighbour's modal coefficients (collapse along the
+//    normal, two tangential sweeps), so no face data ever goes to HBM and
+//    the result is deterministic;
+//  * face integrands are spread onto the Gauss lines normal to the face with
+//    the same end-point Lagrange weights, so volume and face terms are tested
+//    by a single D^T + V^T sweep pass;
+//  * the BR2 lifting uses its closed form at the face points (exact for the
+//    Gauss-rule mass matrix): delta = lambda G,
+//    lambda_q = J_F,q sum_c l(z_c)^2 w_c / detJ(line through q, c);
+//  * curved (Q1) elements recompute the metric from the 8 vertices.
+#include "internal.h"
+#include "physics.h"
+
+namespace dg {
+
+__constant__ Tab c_tab[MAXP + 1];
+__constant__ short c_perm[PERM_TOTAL];
+
+hipError_t upload_tables(const Tab* tabs, const short* perm) {
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof(Tab) * (MAXP + 1));
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_perm), perm, sizeof(short) * PERM_TOTAL);
+}
+
+// ---- geometry -----------------------------------------------------------------
+// Jacobian J[d][k] = dx_d/dxi_k of the trilinear map at reference point x.
+__device__ __forceinline__ void q1_jac(const double* X, double x0, double x1, double x2, double J[3][3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) J[d][0] = J[d][1] = J[d][2] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double s0 = (v & 1) ? 1.0 : -1.0, s1 = (v & 2) ? 1.0 : -1.0, s2 = (v & 4) ? 1.0 : -1.0;
+        const double f0 = 0.5 * (1.0 + s0 * x0), f1 = 0.5 * (1.0 + s1 * x1), f2 = 0.5 * (1.0 + s2 * x2);
+        const double d0 = 0.5 * s0 * f1 * f2, d1 = 0.5 * s1 * f0 * f2, d2 = 0.5 * s2 * f0 * f1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double xv = X[3 * v + d];
+            J[d][0] = fma(d0, xv, J[d][0]);
+            J[d][1] = fma(d1, xv, J[d][1]);
+            J[d][2] = fma(d2, xv, J[d][2]);
+        }
+    }
+}
+
+__device__ __forceinline__ double q1_det(const double J[3][3]) {
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// Ji[k][d] = dxi_k/dx_d; returns det J.
+__device__ __forceinline__ double q1_inv(const double J[3][3], double Ji[3][3]) {
+    const double det = q1_det(J);
+    const double id = 1.0 / det;
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    return det;
+}
+
+__device__ __forceinline__ int nbr_of(const MeshDev& m, int e, int f) {
+    int i = e % m.nx, j = (e / m.nx) % m.ny, k = e / (m.nx * m.ny);
+    const int d = f >> 1, step = (f & 1) ? 1 : -1;
+    if (d == 0) i = (i + step + m.nx) % m.nx;
+    else if (d == 1) j = (j + step + m.ny) % m.ny;
+    else k = (k + step + m.nz) % m.nz;
+    return i + m.nx * (j + m.ny * k);
+}
+
+// ---- sizes and LDS layout per element slot ------------------------------------------
+template <int P>
+struct Sz {
+    static constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NB = 5 * NQ;
+    static constexpr int R0 = (15 * NQ > 60 * NF) ? 15 * NQ : 60 * NF;   // interpolation buffers | collapse
+    static constexpr int OFF_U = R0;                                       // Gauss values (5 NQ)
+    static constexpr int OFF_G = OFF_U + 5 * NQ;                           // Gauss ref. gradients (15 NQ)
+    static constexpr int OFF_E = OFF_G + 15 * NQ;                          // tangential sweep (90 NF) | test-back
+    static constexpr int OFF_F = OFF_E + 90 * NF;                          // face integrands (120 NF)
+    static constexpr int TOT = OFF_F + 120 * NF;
+};
+
+enum { M_RES = 0, M_JVP_FD = 1, M_TANGENT = 2, M_DIAGCOL = 3 };
+
+template <int P, bool DUAL>
+struct Launch;
+template <> struct Launch<1, false> { static constexpr int EPB = 8; };
+template <> struct Launch<1, true> { static constexpr int EPB = 4; };
+template <> struct Launch<2, false> { static constexpr int EPB = 2; };
+template <> struct Launch<2, true> { static constexpr int EPB = 2; };
+template <> struct Launch<3, false> { static constexpr int EPB = 1; };
+template <> struct Launch<3, true> { static constexpr int EPB = 1; };
+template <> struct Launch<4, false> { static constexpr int EPB = 1; };
+template <> struct Launch<4, true> { static constexpr int EPB = 1; };
+
+// tensor index helpers: q = (i0 N + i1) N + i2, i0 <-> xi_1
+template <int N>
+__device__ __forceinline__ int tix(int i0, int i1, int i2) {
+    return (i0 * N + i1) * N + i2;
+}
+template <int N>
+__device__ __forceinline__ int tix_dir(int d, int a, const int ii[3]) {
+    int j[3] = {ii[0], ii[1], ii[2]};
+    j[d] = a;
+    return (j[0] * N + j[1]) * N + j[2];
+}
+
+// dst[c][q] = sum_j M(i_dir(q), j) src[c][q with i_dir -> j] for c < NC;
+// M(i,j) = Tb[i][j] (TR = false) or Tb[j][i] (TR = true).
+template <int N, int NC, bool TR, class T>
+__device__ __forceinline__ void sweep(const double (*Tb)[MAXN], const T* src, T* dst, int dir, const int ii[3],
+                                      int q) {
+    constexpr int NQ = N * N * N;
+    const int i = ii[dir];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        T acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double mij = TR ? Tb[j][i] : Tb[i][j];
+            acc = fma(mij, src[c * NQ + tix_dir<N>(dir, j, ii)], acc);
+        }
+        dst[c * NQ + q] = acc;
+    }
+}
+
+// Load one modal coefficient of element el as the kernel's scalar type.
+template <int MODE, class T>
+__device__ __forceinline__ T load_state(const double* W, const double* v, double h, size_t off, int local, int col,
+                                        bool tangent_on) {
+    const double w = W[off];
+    if constexpr (MODE == M_RES) {
+        return w;
+    } else if constexpr (MODE == M_JVP_FD) {
+        return w + h * v[off];
+    } else if constexpr (MODE == M_TANGENT) {
+        return mk<T>(w, v[off]);
+    } else {
+        return mk<T>(w, (tangent_on && local == col) ? 1.0 : 0.0);
+    }
+}
+
+template <int P, bool NS, bool CURVED, int MODE>
+__global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ))
+    dg_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ V,
+              const double* __restrict__ RW, const double* __restrict__ hbuf, double shift,
+              double* __restrict__ out) {
+    using S_ = Sz<P>;
+    constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = S_::NB;
+    constexpr bool DUAL = (MODE >= M_TANGENT);
+    using T = typename std::conditional<DUAL, Dual, double>::type;
+    constexpr int EPB = Launch<P, DUAL>::EPB;
+    __shared__ T smem[EPB * S_::TOT];
+    __shared__ double sdet[EPB][NQ];
+    __shared__ double svtx[EPB][24];
+
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int tid = threadIdx.x;
+    const int es = tid / NQ, q = tid % NQ;
+    const int e = blockIdx.x * EPB + es;
+    const bool active = e < m.ne;
+    const int col = (MODE == M_DIAGCOL) ? (int)blockIdx.y : -1;
+    double h = 0.0;
+    if constexpr (MODE == M_JVP_FD) {
+        h = hbuf[0];
+        if (h == 0.0) {       // v == 0: y = shift M v = 0 (uniform across the grid)
+            if (active)
+                for (int a = 0; a < 5; ++a) out[(size_t)e * NB + a * NQ + perm[q]] = 0.0;
+            return;
+        }
+    }
+    T* S = smem + es * S_::TOT;
+    const int ii[3] = {q / NF, (q / N) % N, q % N};
+
+    // ---- load own modal coefficients (tensor order) --------------------------------
+    if (active) {
+        const size_t base = (size_t)e * NB;
+        const int pm = perm[q];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+            S[a * NQ + q] = load_state<MODE, T>(W, V, h, base + a * NQ + pm, a * NQ + pm, col, true);
+        if constexpr (CURVED)
+            for (int k = q; k < 24; k += NQ) svtx[es][k] = m.vtx[(size_t)e * 24 + k];
+    }
+    __syncthreads();
+    // ---- interpolation to the Gauss points ---------------------------------------
+    T* X1 = S + 5 * NQ;
+    T* X2 = S + 10 * NQ;
+    T* su = S + S_::OFF_U;
+    T* sg = S + S_::OFF_G;
+    if (active) sweep<N, 5, false>(tb.V, S, X1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X1, X2, 1, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X2, su, 2, ii, q);
+    __syncthreads();
+
+    // ---- volume: gradients, metric, flux ------------------------------------------------
+    T A[5][3], B[5];
+    double detJ = 1.0, Ji[3][3];
+    const double hx = m.h[0], hy = m.h[1], hz = m.h[2];
+    if (active) {
+        T u[5], gx[5][3];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            u[a] = su[a * NQ + q];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc = fma(tb.D[ii[k]][j], su[a * NQ + tix_dir<N>(k, j, ii)], acc);
+                gx[a][k] = acc;
+                sg[(a * 3 + k) * NQ + q] = acc;
+            }
+        }
+        if constexpr (CURVED) {
+            double J[3][3];
+            q1_jac(svtx[es], tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
+            detJ = q1_inv(J, Ji);
+            sdet[es][q] = detJ;
+        } else {
+            detJ = 0.125 * hx * hy * hz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Ji[k][d] = 0.0;
+            Ji[0][0] = 2.0 / hx;
+            Ji[1][1] = 2.0 / hy;
+            Ji[2][2] = 2.0 / hz;
+        }
+        const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]];
+        T F[5][3];
+        flux_c(u, gas.gamma - 1.0, F);
+        if constexpr (NS) {
+            T g[5][3];
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    g[a][j] = Ji[0][j] * gx[a][0] + Ji[1][j] * gx[a][1] + Ji[2][j] * gx[a][2];
+            flux_v_acc(u, g, gas, 1.0, F);
+        }
+        const double c = -wq * detJ;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) A[a][k] = c * (Ji[k][0] * F[a][0] + Ji[k][1] * F[a][1] + Ji[k][2] * F[a][2]);
+            if constexpr (DUAL) B[a] = Dual(0.0, shift * wq * detJ * tan_(u[a]));
+            else B[a] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // ---- faces ------------------------------------------------------------------
+    T* sC = S;                    // collapse of the neighbour modal data (60 NF)
+    T* sE = S + S_::OFF_E;        // after the first tangential sweep (90 NF)
+    T* sF = S + S_::OFF_F;        // face integrands (120 NF)
+    if (active) {
+        for (int fp = q; fp < 6 * NF; fp += NQ) {
+            const int f = fp / NF, fq = fp % NF;
+            const int d = f >> 1, s = f & 1;
+            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            const int nb = nbr_of(m, e, f);
+            const size_t nbase = (size_t)nb * NB;
+            const int tb0 = (fq / N) * st1 + (fq % N) * st2;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                T c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int pm = perm[tb0 + k * sd];
+                    const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm, a * NQ + pm, col, nb == e);
+                    c0 = fma(tb.Le[1 - s][k], val, c0);
+                    c1 = fma(tb.Lde[1 - s][k], val, c1);
+                }
+                sC[(f * NF + fq) * 10 + a * 2 + 0] = c0;
+                sC[(f * NF + fq) * 10 + a * 2 + 1] = c1;
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        for (int fp = q; fp < 6 * NF; fp += NQ) {
+            const int f = fp / NF, fq = fp % NF;
+            const int qt1 = fq / N, cc = fq % N;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                T e0 = 0.0, e0d = 0.0, e1 = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const T* cb = sC + (f * NF + b * N + cc) * 10 + a * 2;
+                    e0 = fma(tb.V[qt1][b], cb[0], e0);
+                    e0d = fma(tb.Vd[qt1][b], cb[0], e0d);
+                    e1 = fma(tb.V[qt1][b], cb[1], e1);
+                }
+                T* eo = sE + (f * NF + fq) * 15 + a * 3;
+                eo[0] = e0;
+                eo[1] = e0d;
+                eo[2] = e1;
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        for (int fp = q; fp < 6 * NF; fp += NQ) {
+            const int f = fp / NF, fq = fp % NF;
+            const int d = f >> 1, s = f & 1;
+            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            const int qt1 = fq / N, qt2 = fq % N;
+            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            T um[5], gxm[5][3], up[5], gxp[5][3];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                T v0 = 0.0, vt1 = 0.0, vt2 = 0.0, vd = 0.0;
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    const T* eo = sE + (f * NF + qt1 * N + c) * 15 + a * 3;
+                    v0 = fma(tb.V[qt2][c], eo[0], v0);
+                    vt1 = fma(tb.V[qt2][c], eo[1], vt1);
+                    vt2 = fma(tb.Vd[qt2][c], eo[0], vt2);
+                    vd = fma(tb.V[qt2][c], eo[2], vd);
+                }
+                um[a] = v0;
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) gxm[a][kk] = (kk == d) ? vd : ((kk == t1) ? vt1 : vt2);
+            }
+            const int tl = qt1 * st1 + qt2 * st2;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                T v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int t = tl + k * sd;
+                    const double l = tb.lag[s][k];
+                    v0 = fma(l, su[a * NQ + t], v0);
+                    g0 = fma(l, sg[(a * 3 + 0) * NQ + t], g0);
+                    g1 = fma(l, sg[(a * 3 + 1) * NQ + t], g1);
+                    g2 = fma(l, sg[(a * 3 + 2) * NQ + t], g2);
+                }
+                up[a] = v0;
+                gxp[a][0] = g0;
+                gxp[a][1] = g1;
+                gxp[a][2] = g2;
+            }
+            // geometry of the face point seen from both sides
+            double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
+            const double sgn = s ? 1.0 : -1.0;
+            if constexpr (CURVED) {
+                const double z1 = tb.z[qt1], z2 = tb.z[qt2];
+                double xi[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
+                double J[3][3];
+                q1_jac(svtx[es], xi[0], xi[1], xi[2], J);
+                q1_inv(J, Jip);
+                // tangents dx/dxi_{d+1}, dx/dxi_{d+2} (cyclic): their cross product points to +xi_d
+                const int da = (d + 1) % 3, db = (d + 2) % 3;
+                double ta[3], tbv[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    ta[kk] = (da == 0) ? J[kk][0] : ((da == 1) ? J[kk][1] : J[kk][2]);
+                    tbv[kk] = (db == 0) ? J[kk][0] : ((db == 1) ? J[kk][1] : J[kk][2]);
+                }
+                const double cx = ta[1] * tbv[2] - ta[2] * tbv[1];
+                const double cy = ta[2] * tbv[0] - ta[0] * tbv[2];
+                const double cz = ta[0] * tbv[1] - ta[1] * tbv[0];
+                JF = sqrt(cx * cx + cy * cy + cz * cz);
+                nrm[0] = sgn * cx / JF;
+                nrm[1] = sgn * cy / JF;
+                nrm[2] = sgn * cz / JF;
+                const double* vn = m.vtx + (size_t)nbr_of(m, e, f) * 24;
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? -sgn : ((kk == t1) ? z1 : z2);
+                q1_jac(vn, xi[0], xi[1], xi[2], J);
+                q1_inv(J, Jim);
+                double sp = 0.0, sm = 0.0;
+                for (int k = 0; k < N; ++k) {
+                    sp += tb.br2[s][k] / sdet[es][tl + k * sd];
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
+                    q1_jac(vn, xi[0], xi[1], xi[2], J);
+                    sm += tb.br2[1 - s][k] / q1_det(J);
+                }
+                lam_p = JF * sp;
+                lam_m = JF * sm;
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) nrm[kk] = (kk == d) ? sgn : 0.0;
+                JF = 0.25 * ((d == 0) ? hy * hz : ((d == 1) ? hx * hz : hx * hy));
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) Jip[k][dd] = 0.0;
+                Jip[0][0] = 2.0 / hx;
+                Jip[1][1] = 2.0 / hy;
+                Jip[2][2] = 2.0 / hz;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) Jim[k][dd] = Jip[k][dd];
+                lam_p = lam_m = 0.5 * N * N * JF / detJ;
+            }
+            const double sc = tb.w[qt1] * tb.w[qt2] * JF;
+            T Fh[5];
+            roe_flux(up, um, nrm, gas.gamma, Fh);
+            T* fo = sF + (f * NF + fq) * 20;
+            if constexpr (NS) {
+                T gp[5][3], gm[5][3], X[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    const T jmp = up[a] - um[a];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        gp[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
+                        gm[a][j] = Jim[0][j] * gxm[a][0] + Jim[1][j] * gxm[a][1] + Jim[2][j] * gxm[a][2];
+                        X[a][j] = jmp * nrm[j];
+                    }
+                }
+                T Fv[5][3], Gp[5][3], Gm[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Fv[a][j] = Gp[a][j] = Gm[a][j] = 0.0;
+                flux_v_acc(up, gp, gas, 0.5, Fv);
+                flux_v_acc(um, gm, gas, 0.5, Fv);
+                flux_v_acc(up, X, gas, -0.5, Gp);     // G+ = 1/2 K(u+)(n+ (x) [u]) = -1/2 F_v(u+, [u] (x) n+)
+                flux_v_acc(um, X, gas, -0.5, Gm);
+                const double cp = 0.5 * gas.eta * lam_p, cm = 0.5 * gas.eta * lam_m;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    T fn = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) fn = fn + (Fv[a][j] + cp * Gp[a][j] + cm * Gm[a][j]) * nrm[j];
+                    fo[a] = sc * (Fh[a] + fn);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        fo[5 + a * 3 + k] = -sc * (Jip[k][0] * Gp[a][0] + Jip[k][1] * Gp[a][1] + Jip[k][2] * Gp[a][2]);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 5; ++a) fo[a] = sc * Fh[a];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- spread face integrands onto the Gauss lines --------------------------------------
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            const double l = tb.lag[s][ii[d]];
+            const T* fo = sF + (f * NF + ii[t1] * N + ii[t2]) * 20;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                B[a] = fma(l, fo[a], B[a]);
+                if constexpr (NS) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) A[a][k] = fma(l, fo[5 + a * 3 + k], A[a][k]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- test: R = V^T (x) V^T (x) V^T [B + sum_k D_k^T A_k] -------------------------------
+    T* sA = S;                    // 15 NQ
+    T* sB = S + 15 * NQ;          // 5 NQ
+    T* H = S + S_::OFF_E;
+    T* Y1 = H + 5 * NQ;
+    T* Y2 = H + 10 * NQ;
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sA[(a * 3 + k) * NQ + q] = A[a][k];
+            sB[a * NQ + q] = B[a];
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            T acc = sB[a * NQ + q];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                    acc = fma(tb.D[j][ii[k]], sA[(a * 3 + k) * NQ + tix_dir<N>(k, j, ii)], acc);
+            H[a * NQ + q] = acc;
+        }
+    }
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, H, Y1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, Y1, Y2, 1, ii, q);
+    __syncthreads();
+    T res[5];
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            T acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], Y2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+            res[a] = acc;
+        }
+    }
+    // ---- output -------------------------------------------------------------------------
+    const size_t base = (size_t)e * NB;
+    const int pm = perm[q];
+    if constexpr (MODE == M_RES) {
+        if (active)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) out[base + a * NQ + pm] = res[a];
+    } else if constexpr (MODE == M_TANGENT) {
+        if (active)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) out[base + a * NQ + pm] = tan_(res[a]);
+    } else if constexpr (MODE == M_DIAGCOL) {
+        if (active)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) out[((size_t)e * NB + col) * NB + a * NQ + pm] = tan_(res[a]);
+    } else {
+        // y = shift M v + (R(W + h v) - R(W)) / h
+        double mv[5];
+        if constexpr (CURVED) {
+            __syncthreads();
+            T* V0 = S;
+            T* V1 = S + 5 * NQ;
+            T* V2 = S + 10 * NQ;
+            if (active)
+#pragma unroll
+                for (int a = 0; a < 5; ++a) V0[a * NQ + q] = V[base + a * NQ + pm];
+            __syncthreads();
+            if (active) sweep<N, 5, false>(tb.V, V0, V1, 0, ii, q);
+            __syncthreads();
+            if (active) sweep<N, 5, false>(tb.V, V1, V2, 1, ii, q);
+            __syncthreads();
+            if (active) {
+                const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]] * detJ;
+                sweep<N, 5, false>(tb.V, V2, V0, 2, ii, q);
+#pragma unroll
+                for (int a = 0; a < 5; ++a) V0[a * NQ + q] = V0[a * NQ + q] * wq;
+            }
+            __syncthreads();
+            if (active) sweep<N, 5, true>(tb.V, V0, V1, 0, ii, q);
+            __syncthreads();
+            if (active) sweep<N, 5, true>(tb.V, V1, V2, 1, ii, q);
+            __syncthreads();
+            if (active)
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], V2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+                    mv[a] = acc;
+                }
+        } else {
+            if (active)
+#pragma unroll
+                for (int a = 0; a < 5; ++a) mv[a] = detJ * V[base + a * NQ + pm];
+        }
+        if (active) {
+            const double ih = 1.0 / h;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const size_t o = base + a * NQ + pm;
+                out[o] = (res[a] - RW[o]) * ih + shift * mv[a];
+            }
+        }
+    }
+}
+
+// ---- mass matrix, projection, quadrature points, Jacobian check --------------------------
+// y = scale * M v (+ y if accumulate).  Affine: M = detJ I.
+template <int P, bool CURVED>
+__global__ void __launch_bounds__((Launch<P, false>::EPB * Sz<P>::NQ))
+    mass_kernel(MeshDev m, const double* __restrict__ v, double* __restrict__ y, double scale, int accumulate) {
+    using S_ = Sz<P>;
+    constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = S_::NB;
+    constexpr int EPB = Launch<P, false>::EPB;
+    __shared__ double smem[EPB][15 * NQ];
+    __shared__ double svtx[EPB][24];
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const int e = blockIdx.x * EPB + es;
+    const bool active = e < m.ne;
+    const int ii[3] = {q / NF, (q / N) % N, q % N};
+    const size_t base = (size_t)e * NB;
+    const int pm = perm[q];
+    double r[5];
+    if constexpr (!CURVED) {
+        if (!active) return;
+        const double detJ = 0.125 * m.h[0] * m.h[1] * m.h[2];
+        for (int a = 0; a < 5; ++a) r[a] = scale * detJ * v[base + a * NQ + pm];
+    } else {
+        double* V0 = smem[es];
+        double* V1 = V0 + 5 * NQ;
+        double* V2 = V0 + 10 * NQ;
+        if (active) {
+            for (int a = 0; a < 5; ++a) V0[a * NQ + q] = v[base + a * NQ + pm];
+            for (int k = q; k < 24; k += NQ) svtx[es][k] = m.vtx[(size_t)e * 24 + k];
+        }
+        __syncthreads();
+        if (active) sweep<N, 5, false>(tb.V, V0, V1, 0, ii, q);
+        __syncthreads();
+        if (active) sweep<N, 5, false>(tb.V, V1, V2, 1, ii, q);
+        __syncthreads();
+        if (active) {
+            double J[3][3];
+            q1_jac(svtx[es], tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
+            const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]] * q1_det(J);
+            sweep<N, 5, false>(tb.V, V2, V0, 2, ii, q);
+            for (int a = 0; a < 5; ++a) V0[a * NQ + q] *= wq;
+        }
+        __syncthreads();
+        if (active) sweep<N, 5, true>(tb.V, V0, V1, 0, ii, q);
+        __syncthreads();
+        if (active) sweep<N, 5, true>(tb.V, V1, V2, 1, ii, q);
+        __syncthreads();
+        if (!active) return;
+        for (int a = 0; a < 5; ++a) {
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], V2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+            r[a] = scale * acc;
+        }
+    }
+    for (int a = 0; a < 5; ++a) {
+        const size_t o = base + a * NQ + pm;
+        y[o] = accumulate ? y[o] + r[a] : r[a];
+    }
+}
+
+// Physical Gauss point coordinates: xyz[e][q][3].
+template <int P>
+__global__ void quad_points_kernel(MeshDev m, double* __restrict__ xyz) {
+    constexpr int N = P + 1, NQ = N * N * N, NF = N * N;
+    const Tab& tb = c_tab[P];
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)m.ne * NQ) return;
+    const int e = (int)(gid / NQ), q = (int)(gid % NQ);
+    const double x0 = tb.z[q / NF], x1 = tb.z[(q / N) % N], x2 = tb.z[q % N];
+    double X[3] = {0.0, 0.0, 0.0};
+    if (m.vtx) {
+        const double* vv = m.vtx + (size_t)e * 24;
+        for (int v = 0; v < 8; ++v) {
+            const double s0 = (v & 1) ? 1.0 : -1.0, s1 = (v & 2) ? 1.0 : -1.0, s2 = (v & 4) ? 1.0 : -1.0;
+            const double Nv = 0.125 * (1.0 + s0 * x0) * (1.0 + s1 * x1) * (1.0 + s2 * x2);
+            for (int d = 0; d < 3; ++d) X[d] = fma(Nv, vv[3 * v + d], X[d]);
+        }
+    }
+    for (int d = 0; d < 3; ++d) xyz[gid * 3 + d] = X[d];
+}
+
+// W = M^-1 int phi u with the Gauss rule: since V is square and
+// V^T diag(w) V = I, this is W = V^T diag(w) u_q independent of detJ.
+template <int P>
+__global__ void project_kernel(MeshDev m, const double* __restrict__ vals, double* __restrict__ W) {
+    using S_ = Sz<P>;
+    constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = S_::NB;
+    constexpr int EPB = Launch<P, false>::EPB;
+    __shared__ double smem[EPB][15 * NQ];
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const int e = blockIdx.x * EPB + es;
+    const bool active = e < m.ne;
+    const int ii[3] = {q / NF, (q / N) % N, q % N};
+    double* V0 = smem[es];
+    double* V1 = V0 + 5 * NQ;
+    double* V2 = V0 + 10 * NQ;
+    if (active) {
+        const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]];
+        for (int a = 0; a < 5; ++a) V0[a * NQ + q] = wq * vals[((size_t)e * NQ + q) * 5 + a];
+    }
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, V0, V1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, V1, V2, 1, ii, q);
+    __syncthreads();
+    if (!active) return;
+    for (int a = 0; a < 5; ++a) {
+        double acc = 0.0;
+        for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], V2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+        W[(size_t)e * NB + a * NQ + perm[q]] = acc;
+    }
+}
+
+// bad[0] += 1 for every volume Gauss point or face point with detJ <= 0.
+template <int P>
+__global__ void check_jac_kernel(MeshDev m, int* bad) {
+    constexpr int N = P + 1, NQ = N * N * N, NF = N * N;
+    const Tab& tb = c_tab[P];
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)m.ne * NQ) return;
+    const int e = (int)(gid / NQ), q = (int)(gid % NQ);
+    double J[3][3];
+    q1_jac(m.vtx + (size_t)e * 24, tb.z[q / NF], tb.z[(q / N) % N], tb.z[q % N], J);
+    const double det = q1_det(J);
+    if (!(det > 0.0)) atomicAdd(bad, 1);
+}
+
+// ---- host launchers -------------------------------------------------------------------------
+namespace {
+template <int P, int MODE>
+hipError_t launch_dg(const DGArgs& a, const double* W, const double* V, const double* RW, const double* hbuf,
+                     double shift, double* out, hipStream_t s) {
+    constexpr bool DUAL = MODE >= M_TANGENT;
+    constexpr int EPB = Launch<P, DUAL>::EPB;
+    constexpr int NQ = Sz<P>::NQ;
+    dim3 grid((a.m.ne + EPB - 1) / EPB, MODE == M_DIAGCOL ? Sz<P>::NB : 1);
+    dim3 block(EPB * NQ);
+    const bool curved = a.m.vtx != nullptr;
+    if (a.ns) {
+        if (curved) hipLaunchKernelGGL((dg_kernel<P, true, true, MODE>), grid, block, 0, s, a.m, a.g, W, V, RW, hbuf, shift, out);
+        else hipLaunchKernelGGL((dg_kernel<P, true, false, MODE>), grid, block, 0, s, a.m, a.g, W, V, RW, hbuf, shift, out);
+    } else {
+        if (curved) hipLaunchKernelGGL((dg_kernel<P, false, true, MODE>), grid, block, 0, s, a.m, a.g, W, V, RW, hbuf, shift, out);
+        else hipLaunchKernelGGL((dg_kernel<P, false, false, MODE>), grid, block, 0, s, a.m, a.g, W, V, RW, hbuf, shift, out);
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t dispatch_dg(const DGArgs& a, const double* W, const double* V, const double* RW, const double* hbuf,
+                       double shift, double* out, hipStream_t s) {
+    switch (a.p) {
+        case 1: return launch_dg<1, MODE>(a, W, V, RW, hbuf, shift, out, s);
+        case 2: return launch_dg<2, MODE>(a, W, V, RW, hbuf, shift, out, s);
+        case 3: return launch_dg<3, MODE>(a, W, V, RW, hbuf, shift, out, s);
+        case 4: return launch_dg<4, MODE>(a, W, V, RW, hbuf, shift, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+hipError_t launch_mass_p(const DGArgs& a, const double* v, double* y, double scale, int acc, hipStream_t s) {
+    constexpr int EPB = Launch<P, false>::EPB;
+    dim3 grid((a.m.ne + EPB - 1) / EPB), block(EPB * Sz<P>::NQ);
+    if (a.m.vtx) hipLaunchKernelGGL((mass_kernel<P, true>), grid, block, 0, s, a.m, v, y, scale, acc);
+    else hipLaunchKernelGGL((mass_kernel<P, false>), grid, block, 0, s, a.m, v, y, scale, acc);
+    return hipGetLastError();
+}
+template <int P>
+hipError_t launch_project_p(const DGArgs& a, const double* vals, double* W, hipStream_t s) {
+    constexpr int EPB = Launch<P, false>::EPB;
+    dim3 grid((a.m.ne + EPB - 1) / EPB), block(EPB * Sz<P>::NQ);
+    hipLaunchKernelGGL((project_kernel<P>), grid, block, 0, s, a.m, vals, W);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_residual(const DGArgs& a, const double* W, double* R, hipStream_t s) {
+    return dispatch_dg<M_RES>(a, W, nullptr, nullptr, nullptr, 0.0, R, s);
+}
+hipError_t launch_jvp_fd(const DGArgs& a, const double* W, const double* RW, const double* v, const double* hbuf,
+                         double shift, double* y, hipStream_t s) {
+    return dispatch_dg<M_JVP_FD>(a, W, v, RW, hbuf, shift, y, s);
+}
+hipError_t launch_jvp_exact(const DGArgs& a, const double* W, const double* v, double shift, double* y,
+                            hipStream_t s) {
+    return dispatch_dg<M_TANGENT>(a, W, v, nullptr, nullptr, shift, y, s);
+}
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, hipStream_t s) {
+    return dispatch_dg<M_DIAGCOL>(a, W, nullptr, nullptr, nullptr, shift, blocks, s);
+}
+hipError_t launch_mass(const DGArgs& a, const double* v, double* y, double scale, int accumulate, hipStream_t s) {
+    switch (a.p) {
+        case 1: return launch_mass_p<1>(a, v, y, scale, accumulate, s);
+        case 2: return launch_mass_p<2>(a, v, y, scale, accumulate, s);
+        case 3: return launch_mass_p<3>(a, v, y, scale, accumulate, s);
+        case 4: return launch_mass_p<4>(a, v, y, scale, accumulate, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_project(const DGArgs& a, const double* vals, double* W, hipStream_t s) {
+    switch (a.p) {
+        case 1: return launch_project_p<1>(a, vals, W, s);
+        case 2: return launch_project_p<2>(a, vals, W, s);
+        case 3: return launch_project_p<3>(a, vals, W, s);
+        case 4: return launch_project_p<4>(a, vals, W, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_quad_points(const DGArgs& a, double* xyz, hipStream_t s) {
+    const size_t n = (size_t)a.m.ne * (a.p + 1) * (a.p + 1) * (a.p + 1);
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (a.p) {
+        case 1: hipLaunchKernelGGL(quad_points_kernel<1>, grid, block, 0, s, a.m, xyz); break;
+        case 2: hipLaunchKernelGGL(quad_points_kernel<2>, grid, block, 0, s, a.m, xyz); break;
+        case 3: hipLaunchKernelGGL(quad_points_kernel<3>, grid, block, 0, s, a.m, xyz); break;
+        case 4: hipLaunchKernelGGL(quad_points_kernel<4>, grid, block, 0, s, a.m, xyz); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s) {
+    const size_t n = (size_t)a.m.ne * (a.p + 1) * (a.p + 1) * (a.p + 1);
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (a.p) {
+        case 1: hipLaunchKernelGGL(check_jac_kernel<1>, grid, block, 0, s, a.m, bad); break;
+        case 2: hipLaunchKernelGGL(check_jac_kernel<2>, grid, block, 0, s, a.m, bad); break;
+        case 3: hipLaunchKernelGGL(check_jac_kernel<3>, grid, block, 0, s, a.m, bad); break;
+        case 4: hipLaunchKernelGGL(check_jac_kernel<4>, grid, block, 0, s, a.m, bad); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dg

@@ -1,0 +1,112 @@
+// Internal declarations of the MI355X DG library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "physics.h"
+
+namespace dg {
+
+constexpr int MAXP = 4;      // supported polynomial degrees 1..MAXP
+constexpr int MAXN = MAXP + 1;
+
+// 1D reference tables of degree P (n = P+1 Gauss points, orthonormal
+// Legendre modes).  Index conventions: q = Gauss point, a = mode, s = end
+// (0: xi = -1, 1: xi = +1).
+struct Tab {
+    double V[MAXN][MAXN];     // V[q][a]  = L_a(z_q)
+    double Vd[MAXN][MAXN];    // Vd[q][a] = L_a'(z_q)
+    double D[MAXN][MAXN];     // D[q][r]  = l_r'(z_q), collocation derivative on the Gauss points
+    double w[MAXN];           // Gauss weights
+    double z[MAXN];           // Gauss points
+    double lag[2][MAXN];      // l_q(-1), l_q(+1): Lagrange basis of the Gauss points at the ends
+    double Le[2][MAXN];       // L_a(-1), L_a(+1)
+    double Lde[2][MAXN];      // L_a'(-1), L_a'(+1)
+    double br2[2][MAXN];      // (sum_i L_i(+-1) L_i(z_q))^2 w_q: BR2 line weights
+};
+
+// perm offsets: tensor-mode tables of every P packed in one array
+constexpr int perm_offset(int P) { return P == 1 ? 0 : P == 2 ? 8 : P == 3 ? 35 : 99; }
+constexpr int PERM_TOTAL = 224;
+
+// Host construction (tables.cpp).
+void build_tables(Tab tabs[MAXP + 1], short perm[PERM_TOTAL]);
+// Upload to the device constant memory of the current device (dg_kernels.hip).
+hipError_t upload_tables(const Tab* tabs, const short* perm);
+
+struct MeshDev {
+    int nx, ny, nz, ne;
+    double h[3];              // straight box spacing
+    const double* vtx;        // device [ne][8][3] (curved only) or nullptr
+};
+
+// Kernel launch parameters shared by the DG kernels.
+struct DGArgs {
+    MeshDev m;
+    Gas g;                    // physics.h
+    int p;
+    bool ns;
+};
+
+// ---- DG kernels (dg_kernels.hip) ------------------------------------------
+hipError_t launch_residual(const DGArgs& a, const double* W, double* R, hipStream_t s);
+hipError_t launch_jvp_fd(const DGArgs& a, const double* W, const double* RW, const double* v, const double* hbuf,
+                         double shift, double* y, hipStream_t s);
+hipError_t launch_jvp_exact(const DGArgs& a, const double* W, const double* v, double shift, double* y,
+                            hipStream_t s);
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, hipStream_t s);
+// Coarse face-coupling blocks: for every element e, face f, the (nbc x nbc)
+// block dR_e[S]/dW_nb(f)[S] over the coarse-mode set S of degree pc (rows and
+// columns equation-major over S), column-major.  out [ne][6][nbc][nbc].
+hipError_t launch_offdiag_blocks(const DGArgs& a, const double* W, int pc, double* out, hipStream_t s);
+hipError_t launch_mass(const DGArgs& a, const double* v, double* y, double scale, int accumulate, hipStream_t s);
+hipError_t launch_quad_points(const DGArgs& a, double* xyz, hipStream_t s);
+hipError_t launch_project(const DGArgs& a, const double* vals, double* W, hipStream_t s);
+hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s);
+
+// ---- vector / reduction kernels (la_kernels.hip) ----------------------------
+// Deterministic sums: fixed grid, fixed per-block order, fixed second stage.
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+// out[k] = <x_k, y> for k < nx (x_k = X + k*ldx), written to device out.
+hipError_t launch_multi_dot(const double* X, size_t ldx, int nx, const double* y, size_t n, double* partial,
+                            double* out, hipStream_t s);
+hipError_t launch_dot(const double* x, const double* y, size_t n, double* partial, double* out, hipStream_t s);
+// h = eps sqrt(1 + sqrt(nw2)) / sqrt(nv2), 0 if nv2 == 0
+hipError_t launch_fd_step(const double* nw2, const double* nv2, double eps, double* h, hipStream_t s);
+hipError_t launch_axpby(size_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s);
+// y += sum_k c[k] * X_k   (c on device), or y -= when sign < 0
+hipError_t launch_multi_axpy(size_t n, int k, const double* c, int sign, const double* X, size_t ldx, double* y,
+                             hipStream_t s);
+// y = x * (*sc) with sc on device (sc inverted when invert != 0)
+hipError_t launch_scale_dev(size_t n, const double* x, const double* sc, int invert, double* y, hipStream_t s);
+hipError_t launch_copy(size_t n, const double* x, double* y, hipStream_t s);
+hipError_t launch_fill(size_t n, double v, double* y, hipStream_t s);
+// restriction: coarse[e][a][i] = fine[e][a][i], i < nvc; prolongation adds/overwrites
+hipError_t launch_restrict(int ne, int nvf, int nvc, const double* fine, double* coarse, hipStream_t s);
+hipError_t launch_prolong_add(int ne, int nvf, int nvc, const double* coarse, double* fine, int overwrite,
+                              hipStream_t s);
+hipError_t launch_count_nonfinite(size_t n, const double* x, int* flag, hipStream_t s);
+
+// ---- dense block kernels (lu_kernels.hip) ------------------------------------
+template <class TF>
+hipError_t launch_lu(TF* A, int* piv, int nblk, int n, hipStream_t s);
+// z = D^-1 r for every block, factors in TF, vectors FP64; z may not alias r
+template <class TF>
+hipError_t launch_lu_solve(const TF* LU, const int* piv, const double* r, double* z, int nblk, int n,
+                           hipStream_t s);
+// Extract coarse principal sub-blocks (FP64 column-major fine blocks) and round to TF.
+template <class TF>
+hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);
+// Block-sparse product y = K x with 7 blocks per element row (diagonal + 6 faces)
+template <class TF>
+hipError_t launch_bsr7(const DGArgs& a, const TF* diag, const TF* off, const double* x, double* y, int nbc,
+                       hipStream_t s);
+hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s);
+
+}  // namespace dg

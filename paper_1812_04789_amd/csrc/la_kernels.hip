@@ -1,0 +1,269 @@
+// Vector kernels for the Krylov solvers and the p-multigrid transfer
+// (Sec. 6, flexible GMRES; Sec. 6.1 restriction/prolongation).
+//
+// Reductions are deterministic: a fixed grid of RED_BLOCKS blocks, each
+// summing a fixed grid-stride subset in a fixed order and reducing its
+// threads by a fixed tree, then one block per output summing the partials in
+// a fixed tree.  Results are bitwise reproducible run to run and independent
+// of what else shares the device.
+#include "internal.h"
+
+namespace dg {
+
+namespace {
+constexpr int KCH = 8;    // dot products per pass of the multi-dot
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(RED_THREADS)
+    multi_dot_stage1(const double* __restrict__ X, size_t ldx, int k0, int kn, const double* __restrict__ y, size_t n,
+                     double* __restrict__ partial) {
+    __shared__ double sh[RED_THREADS];
+    double acc[KCH];
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) acc[c] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double yi = y[i];
+#pragma unroll
+        for (int c = 0; c < KCH; ++c)
+            if (c < kn) acc[c] = fma(X[(size_t)(k0 + c) * ldx + i], yi, acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) {
+        if (c < kn) {
+            const double s = block_sum(acc[c], sh);
+            if (threadIdx.x == 0) partial[(size_t)(k0 + c) * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) sum_stage2(const double* __restrict__ partial, int nparts,
+                                                          double* __restrict__ out) {
+    __shared__ double sh[RED_THREADS];
+    const double* p = partial + (size_t)blockIdx.x * nparts;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += p[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+hipError_t launch_multi_dot(const double* X, size_t ldx, int nx, const double* y, size_t n, double* partial,
+                            double* out, hipStream_t s) {
+    for (int k0 = 0; k0 < nx; k0 += KCH) {
+        const int kn = (nx - k0 < KCH) ? nx - k0 : KCH;
+        hipLaunchKernelGGL(multi_dot_stage1, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, ldx, k0, kn, y, n, partial);
+    }
+    hipLaunchKernelGGL(sum_stage2, dim3(nx), dim3(RED_THREADS), 0, s, partial, RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const double* x, const double* y, size_t n, double* partial, double* out, hipStream_t s) {
+    return launch_multi_dot(x, n, 1, y, n, partial, out, s);
+}
+
+__global__ void fd_step_kernel(const double* nw2, const double* nv2, double eps, double* h) {
+    const double nv = sqrt(nv2[0]);
+    h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2[0])) / nv : 0.0;
+}
+hipError_t launch_fd_step(const double* nw2, const double* nv2, double eps, double* h, hipStream_t s) {
+    hipLaunchKernelGGL(fd_step_kernel, dim3(1), dim3(1), 0, s, nw2, nv2, eps, h);
+    return hipGetLastError();
+}
+
+__global__ void axpby_kernel(size_t n, double a, const double* __restrict__ x, double b, const double* y,
+                             double* z) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double yi = (b != 0.0) ? b * y[i] : 0.0;
+        z[i] = fma(a, x[i], yi);
+    }
+}
+static dim3 grid_for(size_t n) {
+    size_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g == 0) g = 1;
+    return dim3((unsigned)g);
+}
+hipError_t launch_axpby(size_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, grid_for(n), dim3(256), 0, s, n, a, x, b, y, z);
+    return hipGetLastError();
+}
+
+// y (+/-)= sum_k c[k] X_k, coefficients read from device memory
+__global__ void multi_axpy_kernel(size_t n, int k, const double* __restrict__ c, int sign,
+                                  const double* __restrict__ X, size_t ldx, double* __restrict__ y) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(c[j], X[(size_t)j * ldx + i], acc);
+        y[i] = (sign < 0) ? y[i] - acc : y[i] + acc;
+    }
+}
+hipError_t launch_multi_axpy(size_t n, int k, const double* c, int sign, const double* X, size_t ldx, double* y,
+                             hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(multi_axpy_kernel, grid_for(n), dim3(256), 0, s, n, k, c, sign, X, ldx, y);
+    return hipGetLastError();
+}
+
+__global__ void scale_dev_kernel(size_t n, const double* __restrict__ x, const double* __restrict__ sc, int invert,
+                                 double* __restrict__ y) {
+    const double a = invert ? ((sc[0] != 0.0) ? 1.0 / sc[0] : 0.0) : sc[0];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i];
+}
+hipError_t launch_scale_dev(size_t n, const double* x, const double* sc, int invert, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(scale_dev_kernel, grid_for(n), dim3(256), 0, s, n, x, sc, invert, y);
+    return hipGetLastError();
+}
+
+__global__ void copy_kernel(size_t n, const double* __restrict__ x, double* __restrict__ y) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = x[i];
+}
+hipError_t launch_copy(size_t n, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, grid_for(n), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+__global__ void fill_kernel(size_t n, double v, double* __restrict__ y) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = v;
+}
+hipError_t launch_fill(size_t n, double v, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, grid_for(n), dim3(256), 0, s, n, v, y);
+    return hipGetLastError();
+}
+
+// Restriction to the first nvc modes of every (element, equation) run.
+__global__ void restrict_kernel(size_t nc, int nvf, int nvc, const double* __restrict__ fine,
+                                double* __restrict__ coarse) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const size_t run = i / nvc;
+        const int m = (int)(i % nvc);
+        coarse[i] = fine[run * nvf + m];
+    }
+}
+hipError_t launch_restrict(int ne, int nvf, int nvc, const double* fine, double* coarse, hipStream_t s) {
+    const size_t nc = (size_t)ne * 5 * nvc;
+    hipLaunchKernelGGL(restrict_kernel, grid_for(nc), dim3(256), 0, s, nc, nvf, nvc, fine, coarse);
+    return hipGetLastError();
+}
+// Prolongation (zero padding of the fine modes), added to or written over fine.
+__global__ void prolong_kernel(size_t nf, int nvf, int nvc, const double* __restrict__ coarse,
+                               double* __restrict__ fine, int overwrite) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) {
+        const size_t run = i / nvf;
+        const int m = (int)(i % nvf);
+        const double c = (m < nvc) ? coarse[run * nvc + m] : 0.0;
+        fine[i] = overwrite ? c : fine[i] + c;
+    }
+}
+hipError_t launch_prolong_add(int ne, int nvf, int nvc, const double* coarse, double* fine, int overwrite,
+                              hipStream_t s) {
+    const size_t nf = (size_t)ne * 5 * nvf;
+    hipLaunchKernelGGL(prolong_kernel, grid_for(nf), dim3(256), 0, s, nf, nvf, nvc, coarse, fine, overwrite);
+    return hipGetLastError();
+}
+
+__global__ void nonfinite_kernel(size_t n, const double* __restrict__ x, int* flag) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (!isfinite(x[i])) bad = 1;
+    if (bad) atomicOr(flag, 1);
+}
+hipError_t launch_count_nonfinite(size_t n, const double* x, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(nonfinite_kernel, grid_for(n), dim3(256), 0, s, n, x, flag);
+    return hipGetLastError();
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (float)x[i];
+}
+hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(f64_to_f32_kernel, grid_for(n), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+// ---- GMRES small dense algebra on the device ---------------------------------------------
+// Hessenberg column j (length j+2) in Hc (ld = restart+1, column-major) after
+// Gram-Schmidt: apply the previous Givens rotations, build rotation j, update
+// g, store |g[j+1]| in est[0].  A single work-item (the work is O(j)).
+__global__ void givens_kernel(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est) {
+    double* h = H + (size_t)j * ldh;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double r = hypot(a, b);
+    const double c = (r > 0.0) ? a / r : 1.0, sgn = (r > 0.0) ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = sgn;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sgn * g[j];
+    g[j] = c * g[j];
+    est[0] = fabs(g[j + 1]);
+}
+// y = R^-1 g[0:k] for the k x k upper triangle of H.  After a breakdown
+// (zero new direction) the trailing columns are exactly zero: they are dropped.
+__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
+    int ke = k;
+    for (int i = 0; i < k; ++i)
+        if (!(fabs(H[(size_t)i * ldh + i]) > 0.0)) { ke = i; break; }
+    for (int i = ke; i < k; ++i) y[i] = 0.0;
+    for (int i = ke - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int c = i + 1; c < ke; ++c) s -= H[(size_t)c * ldh + i] * y[c];
+        y[i] = s / H[(size_t)i * ldh + i];
+    }
+}
+// Combine the two Gram-Schmidt passes: h[i] += h2[i] (i <= j), set h[j+1] = sqrt(nrm2) and
+// the inverse norm for normalisation.
+__global__ void gs_finish_kernel(double* hcol, const double* h2, int jp1, const double* nrm2, double* inv) {
+    for (int i = 0; i < jp1; ++i) hcol[i] += h2[i];
+    const double nr = sqrt(nrm2[0]);
+    hcol[jp1] = nr;
+    inv[0] = nr;
+}
+__global__ void init_g_kernel(double* g, int len, const double* beta2) {
+    for (int i = 0; i < len; ++i) g[i] = 0.0;
+    g[0] = sqrt(beta2[0]);
+}
+
+hipError_t launch_givens(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est, hipStream_t s) {
+    hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, s, H, ldh, j, cs, sn, g, est);
+    return hipGetLastError();
+}
+hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(1), 0, s, H, ldh, k, g, y);
+    return hipGetLastError();
+}
+hipError_t launch_gs_finish(double* hcol, const double* h2, int jp1, const double* nrm2, double* nrm, hipStream_t s) {
+    hipLaunchKernelGGL(gs_finish_kernel, dim3(1), dim3(1), 0, s, hcol, h2, jp1, nrm2, nrm);
+    return hipGetLastError();
+}
+hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s) {
+    hipLaunchKernelGGL(init_g_kernel, dim3(1), dim3(1), 0, s, g, len, beta2);
+    return hipGetLastError();
+}
+
+}  // namespace dg
