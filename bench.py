@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Benchmark of the implicit modal DG hot path on one MI355X.
+
+A step is one implicit BDF2 time step of the whole hot path: p-multigrid
+setup (diagonal-block assembly, batched PLU), Newton iterations, each solved by
+FGMRES preconditioned with one p-multigrid V-cycle (block-Jacobi smoothing,
+matrix-free level-0 products, coarsest GMRES), residuals and exact Jacobian
+products.  Workload (default): Taylor-Green vortex, Navier-Stokes with BR2,
+Re = 1600, M = 0.1, Pr = 0.71, periodic [0, 2pi]^3, 16^3 hexahedra, p = 3
+(1,310,720 DOF), dt = 0.05, FP64 pMG 3-2-1 with 2 + 2 BJ sweeps, coarsest
+GMRES(BJ) 30, FGMRES(40) to rtol 1e-8.
+
+value = DOF x time steps / second (GDOF/s) over the timed steps, inputs
+resident on the device.  One JSON line is printed.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDOF/s DG J·v; time-step solve s, mixed vs FP64 pMG-FGMRES @ rel 1e-8"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+WORKLOADS = {
+    "tgv_p3_16": dict(n=(16, 16, 16), lo=(0, 0, 0), hi=(2 * math.pi,) * 3, p=3, mach=0.1, mu=1.0 / 1600, Pr=0.71,
+                      curved=0.0, ic="tgv", dt=0.05, levels=[3, 2, 1], restart=40, rtol=1e-8,
+                      desc="Taylor-Green NS/BR2 Re=1600 M=0.1 on a periodic 16^3 hex box, p=3, one BDF2 step dt=0.05, "
+                           "FP64 pMG 3-2-1 (2+2 BJ sweeps, coarsest GMRES(BJ) 30), FGMRES(40) rtol 1e-8"),
+    "tgv_p4_16_curved": dict(n=(16, 16, 16), lo=(0, 0, 0), hi=(2 * math.pi,) * 3, p=4, mach=0.01, mu=1.0 / 1600,
+                             Pr=0.71, curved=0.05, ic="tgv", dt=0.05, levels=[4, 2, 1], restart=40, rtol=1e-8,
+                             desc="Taylor-Green NS/BR2 M=0.01 on a curved 16^3 hex mesh, p=4, one BDF2 step, "
+                                  "pMG 4-2-1, FGMRES(40) rtol 1e-8"),
+    "vortex_p2_4": dict(n=(4, 4, 4), lo=(0, 0, 0), hi=(10.0,) * 3, p=2, mach=0.5, mu=0.0, Pr=0.72, curved=0.0,
+                        ic="vortex", dt=0.1, levels=[2], restart=30, rtol=1e-10,
+                        desc="isentropic vortex Euler p=2 on a periodic 4^3 box, one BDF2 step dt=0.1, "
+                             "FGMRES(30) + element block-Jacobi, rtol 1e-10"),
+}
+
+
+def run(args):
+    import numpy as np
+    import torch
+    from paper_1812_04789_amd import binding, inputs
+
+    wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    vtx = inputs.box_vertices(wl["n"], wl["lo"], wl["hi"], amp=wl["curved"]) if wl["curved"] else None
+    ctx = binding.Context(wl["n"], wl["lo"], wl["hi"], wl["p"], gamma=1.4, mu=wl["mu"], Pr=wl["Pr"], eta=7.0,
+                          vertices=vtx)
+    xq = ctx.quad_points().cpu().numpy()
+    if wl["ic"] == "tgv":
+        vals = inputs.taylor_green(xq, mach=wl["mach"])
+    else:
+        vals = inputs.isentropic_vortex(xq, mach=wl["mach"])
+    W0 = ctx.project(torch.tensor(vals.reshape(-1), device="cuda"))
+    if wl["ic"] == "vortex":
+        W0 += torch.tensor(inputs.uniform_noise((ctx.ne, 5, ctx.nv), 1812, 1e-6).reshape(-1), device="cuda")
+    fopts = binding.fgmres_opts(restart=wl["restart"], rtol=wl["rtol"])
+
+    def popts_for(mixed):
+        prec = binding.DG_FP32 if mixed else binding.DG_FP64
+        return binding.pmg_opts(wl["levels"], prec_fine=prec, prec_coarse=prec)
+
+    def steps(popts, K, W):
+        Wn, Wnm1 = W.clone(), None
+        stats = []
+        for _ in range(K):
+            Wnp1, st = ctx.bdf2_step(Wn, Wnm1, wl["dt"], popts, fopts)
+            stats.append(st)
+            Wnm1, Wn = Wn, Wnp1
+        return Wn, stats
+
+    # ---- FP64 timed steps --------------------------------------------------------
+    popts64 = popts_for(False)
+    steps(popts64, args.warmup, W0)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    W64, st64 = steps(popts64, args.steps, W0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = ctx.timing_read()
+    ctx.timing(False)
+    elapsed = t1 - t0
+    value = ctx.ndof * args.steps / elapsed / 1e9
+
+    # ---- kernel roofline (families measured live over the timed steps) -------------
+    # Algorithmic bytes / flops per launch come from the library (dg_timing_read).
+    fams = {}
+    for kind, (ms, cnt, by, fl) in kern.items():
+        if cnt == 0:
+            continue
+        fams[kind] = dict(ms_total=ms, launches=cnt, ms_avg=ms / cnt, bytes_per_launch=by / cnt,
+                          gbs=(by / (ms * 1e-3) / 1e9) if (by and ms > 0) else None,
+                          tflops=(fl / (ms * 1e-3) / 1e12) if (fl and ms > 0) else None)
+    dom = max(fams, key=lambda k: fams[k]["ms_total"]) if fams else None
+    roof = None
+    if dom:
+        f = fams[dom]
+        if dom == "lu":
+            roof = dict(kernel=dom, bound="alu", achieved=f["tflops"], peak=FP64_PEAK_TFS, unit="TFLOP/s",
+                        frac=f["tflops"] / FP64_PEAK_TFS, traffic=None, ms_avg=f["ms_avg"])
+        else:
+            roof = dict(kernel=dom, bound="hbm", achieved=f["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=f["gbs"] / HBM_PEAK_GBS, traffic=None, ms_avg=f["ms_avg"])
+
+    # ---- J.v throughput (the paper's FD product and the exact product) --------------
+    v = torch.tensor(inputs.random_vector(ctx.ne, ctx.p, seed=7).reshape(-1), device="cuda")
+    RW = ctx.residual(W0)
+    y = ctx.empty()
+    s = torch.cuda.current_stream()
+    jv = {}
+    for name, fn in (("fd", lambda: ctx.jvp(W0, RW, v, 30.0, y)), ("exact", lambda: ctx.jvp_exact(W0, v, 30.0, y)),
+                     ("residual", lambda: ctx.residual(W0, y))):
+        for _ in range(3):
+            fn()
+        ctx.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.jvp_reps):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        kk = ctx.timing_read()
+        ctx.timing(False)
+        kname = {"fd": "jvp_fd", "exact": "jvp_exact", "residual": "residual"}[name]
+        kms, kc = kk[kname][0], kk[kname][1]
+        jv[name] = dict(call_ms=e0.elapsed_time(e1) / args.jvp_reps, kernel_ms=kms / max(kc, 1),
+                        gdof_s=ctx.ndof / (e0.elapsed_time(e1) / args.jvp_reps * 1e-3) / 1e9)
+        by = {"fd": 32.0, "exact": 24.0, "residual": 16.0}[name] * ctx.ndof
+        jv[name]["kernel_gbs"] = by / (jv[name]["kernel_ms"] * 1e-3) / 1e9
+        jv[name]["hbm_frac"] = jv[name]["kernel_gbs"] / HBM_PEAK_GBS
+
+    # ---- mixed precision steps (FP32 block factors) ------------------------------------
+    mixed = None
+    if not args.no_mixed and len(wl["levels"]) > 0:
+        popts32 = popts_for(True)
+        steps(popts32, 1, W0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        W32, st32 = steps(popts32, args.steps, W0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        d = (W32 - W64).norm().item() / W64.norm().item()
+        mixed = dict(time_step_s=(t3 - t2) / args.steps, rel_diff_vs_fp64=d,
+                     linear_iters=[s_.linear_iters for s_ in st32], newton=[s_.newton for s_ in st32],
+                     max_rel_res_true=max(s_.max_rel_res_true for s_ in st32))
+
+    # ---- CPU baseline: the oracle on a bounded sample ---------------------------------
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "tgv_p3_16":
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "description": wl["desc"], "ndof": ctx.ndof,
+                   "elements": ctx.ne, "p": ctx.p, "value_is": "DOF x BDF2 steps per second",
+                   "parallelism": "single GPU"},
+        "time_step_s": {"fp64": elapsed / args.steps, "mixed": mixed["time_step_s"] if mixed else None},
+        "mixed_speedup": (elapsed / args.steps / mixed["time_step_s"]) if mixed else None,
+        "mixed": mixed,
+        "fp64_solver": {"newton": [s_.newton for s_ in st64], "linear_iters": [s_.linear_iters for s_ in st64],
+                        "max_rel_res_true": max(s_.max_rel_res_true for s_ in st64),
+                        "setup_s": [s_.setup_seconds for s_ in st64], "solve_s": [s_.solve_seconds for s_ in st64]},
+        "jvp": jv,
+        "kernels": fams,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline():
+    """The oracle (plain NumPy FP64, as it stands) on one BDF2 step of the same
+    physics and solver settings on a 2 x 1 x 1 mesh of the same periodic box
+    (320 x 2 = 640 DOF), one BLAS thread; DOF x steps / s."""
+    import math as m
+    from threadpoolctl import threadpool_limits
+    from oracle import mesh as omesh, dg as odg, timestep as ots
+    from paper_1812_04789_amd import inputs
+    L = 2 * m.pi
+    mesh = omesh.BoxMesh((2, 1, 1), (0, 0, 0), (L, L, L))
+    D = odg.Discretization(mesh, 3, gamma=1.4, mu=1.0 / 1600, Pr=0.71, eta=7.0)
+    W = D.project(inputs.taylor_green(D.quad_points(), mach=0.1))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        _, st = ots.bdf2_step(D, W, None, 0.05, precond="pmg", levels=[3, 2, 1], restart=40, rtol=1e-8)
+        el = time.perf_counter() - t0
+    return {"value": D.ndof() / el / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": "one BDF2 step (TGV NS p=3, pMG 3-2-1, FGMRES(40) 1e-8) of the oracle on a 2x1x1 mesh "
+                      "of the same box (640 DOF), per-DOF rate; %.1f s wall" % el,
+            "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tgv_p3_16", choices=sorted(WORKLOADS))
+    ap.add_argument("--jvp-reps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the hot path of this build is single-GPU "
+              "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

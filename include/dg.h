@@ -159,8 +159,9 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
 
 /* Batched PLU with partial pivoting (Sec. 6.3), in place, LAPACK convention
  * (column-major blocks, rows k and piv[k] exchanged at step k, unit-lower L
- * below the diagonal).  A device [nblk][n][n], piv device int [nblk][n].
- * Enqueued on hip_stream.  A zero pivot is left in place (no error). */
+ * below the diagonal).  A device [nblk][n][n], piv device int [nblk][n],
+ * 1 <= n <= 625.  Enqueued on hip_stream.  A zero pivot is left in place (no
+ * error). */
 dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n);
 /* x = A^-1 b for every block with the factors of dg_batched_lu; b, x device [nblk][n]. */
 dg_status dg_batched_lu_solve(void* hip_stream, const double* LU, const int* piv, const double* b, double* x,
@@ -192,6 +193,21 @@ dg_status fgmres_step(dg_ctx* ctx, const double* W, const double* RW, const doub
 dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
                        const fgmres_opts* fopts, double newton_rtol, int max_newton, double* Wnp1,
                        dg_step_stats* stats);
+
+/* Per-kernel timing (instrumentation for measurement): while enabled, every
+ * launch of the listed kernel families on the context's stream is bracketed
+ * by HIP events.  dg_timing(ctx, 1) enables and clears, dg_timing(ctx, 0)
+ * disables.  dg_timing_read synchronises the stream and returns, per family,
+ * the summed device time (ms), the launch count and the summed algorithmic
+ * bytes and flops of those launches (what the operation must move/compute:
+ * residual 16 B/DOF, FD J.v 32 B/DOF, exact J.v 24 B/DOF, diagonal blocks the
+ * written blocks, PLU (2/3) n^3 flops and one read + write of the block,
+ * block solve one read of the factors and 16 B per vector entry) since the
+ * last clear, then clears.  All arrays have DG_K_COUNT entries (host memory). */
+enum { DG_K_RESIDUAL = 0, DG_K_JVP_FD = 1, DG_K_JVP_EXACT = 2, DG_K_DIAG_BLOCKS = 3, DG_K_LU = 4,
+       DG_K_LU_SOLVE = 5, DG_K_BSR = 6, DG_K_COUNT = 7 };
+dg_status dg_timing(dg_ctx* ctx, int enable);
+dg_status dg_timing_read(dg_ctx* ctx, double* ms, int* counts, double* bytes, double* flops);
 
 #ifdef __cplusplus
 }

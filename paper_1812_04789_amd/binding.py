@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdg_mi355x.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOCONV, DG_ENONFINITE, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
+KERNEL_KINDS = ["residual", "jvp_fd", "jvp_exact", "diag_blocks", "lu", "lu_solve", "bsr"]
 STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
           -5: "DG_ENONFINITE", -6: "DG_ESTATE"}
 
@@ -71,6 +72,8 @@ SIGNATURES = {
     "pmg_setup": (_I, [_P, _P, _D, ctypes.POINTER(PmgOpts)]),
     "pmg_apply": (_I, [_P, _P, _P]),
     "fgmres_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(FgmresOpts), ctypes.POINTER(FgmresStats)]),
+    "dg_timing": (_I, [_P, _I]),
+    "dg_timing_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "dg_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
                           ctypes.POINTER(StepStats)]),
 }
@@ -241,6 +244,19 @@ class Context:
         if s != DG_OK and (raise_on_noconv or s != DG_ENOCONV):
             self._check(s)
         return x, st
+
+    def timing(self, enable):
+        self._check(self.lib.dg_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        """{kernel family: (total device ms, launches, algorithmic bytes, flops)} since the last clear."""
+        k = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int * k)()
+        by = (ctypes.c_double * k)()
+        fl = (ctypes.c_double * k)()
+        self._check(self.lib.dg_timing_read(self.h, ms, cnt, by, fl))
+        return {KERNEL_KINDS[i]: (ms[i], cnt[i], by[i], fl[i]) for i in range(k)}
 
     def bdf2_step(self, Wn, Wnm1, dt, popts, fopts, newton_rtol=1e-10, max_newton=5, Wnp1=None):
         Wnp1 = self.empty() if Wnp1 is None else Wnp1

@@ -84,10 +84,10 @@ struct Level {
     size_t ndof = 0;
     DBuf<double> f64;     // factors (FP64)
     DBuf<float> f32;      // factors (FP32)
-    DBuf<int> piv;
+    DBuf<int> piv, pos;
     bool use32 = false;
     DBuf<double> x, b, r, t, z;
-    void release() { f64.release(); f32.release(); piv.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
+    void release() { f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
 };
 
 std::mutex g_tab_mu;
@@ -119,6 +119,12 @@ struct dg_ctx {
     Krylov kf;                              // outer FGMRES
     // Newton
     DBuf<double> RW, Ru, xN;
+    // per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;          // pairs (start, stop)
+    std::vector<int> ev_kind;
+    std::vector<double> ev_bytes, ev_flops;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -143,6 +149,32 @@ void fail(dg_ctx* ctx, dg_status st, const std::string& msg) {
 
 double* sc(dg_ctx* ctx, int slot) { return ctx->scal.p + slot; }
 
+// Bracket one launch with events when timing is on.
+template <class F>
+void timed(dg_ctx* ctx, int kind, double bytes, double flops, F&& launch) {
+    if (!ctx->timing) {
+        CK(launch());
+        return;
+    }
+    if (2 * (ctx->ev_used + 1) > ctx->ev.size()) {
+        hipEvent_t a, b;
+        CK(hipEventCreate(&a));
+        CK(hipEventCreate(&b));
+        ctx->ev.push_back(a);
+        ctx->ev.push_back(b);
+        ctx->ev_kind.push_back(0);
+        ctx->ev_bytes.push_back(0.0);
+        ctx->ev_flops.push_back(0.0);
+    }
+    const size_t i = ctx->ev_used++;
+    ctx->ev_kind[i] = kind;
+    ctx->ev_bytes[i] = bytes;
+    ctx->ev_flops[i] = flops;
+    CK(hipEventRecord(ctx->ev[2 * i], ctx->s));
+    CK(launch());
+    CK(hipEventRecord(ctx->ev[2 * i + 1], ctx->s));
+}
+
 double read_scalar(dg_ctx* ctx, const double* dptr) {
     double v = 0.0;
     CK(hipMemcpyAsync(&v, dptr, sizeof(double), hipMemcpyDeviceToHost, ctx->s));
@@ -163,14 +195,17 @@ void jvp_fd(dg_ctx* ctx, const double* W, const double* RW, const double* v, dou
     }
     dot(ctx, v, v, ctx->N, sc(ctx, S_NV2));
     CK(launch_fd_step(nw2, sc(ctx, S_NV2), 1e-7, sc(ctx, S_H), ctx->s));
-    CK(launch_jvp_fd(ctx->a, W, RW, v, sc(ctx, S_H), shift, y, ctx->s));
+    timed(ctx, DG_K_JVP_FD, 32.0 * (double)ctx->N, 0.0, [&] { return launch_jvp_fd(ctx->a, W, RW, v, sc(ctx, S_H), shift, y, ctx->s); });
 }
 
 // ---- p-multigrid ------------------------------------------------------------------
 void bj_apply(dg_ctx* ctx, int l, const double* r, double* z) {
     Level& L = ctx->lv[l];
-    if (L.use32) CK(launch_lu_solve<float>(L.f32.p, L.piv.p, r, z, ctx->ne, L.nb, ctx->s));
-    else CK(launch_lu_solve<double>(L.f64.p, L.piv.p, r, z, ctx->ne, L.nb, ctx->s));
+    const double nbl = L.nb, sf = L.use32 ? 4.0 : 8.0;
+    timed(ctx, DG_K_LU_SOLVE, ctx->ne * (sf * nbl * nbl + 20.0 * nbl), ctx->ne * 2.0 * nbl * nbl, [&] {
+        return L.use32 ? launch_lu_solve_blocked<float>(L.f32.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s)
+                       : launch_lu_solve_blocked<double>(L.f64.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s);
+    });
 }
 
 // y = K_l x (level operator): level 0 the FD product (Eq. DG-mf) at the
@@ -280,6 +315,9 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
         fail(ctx, DG_EINVAL, "assembled coarse operators are not available in this build");
 }
 
+double lu_bytes(dg_ctx* ctx, int nb, double s) { return ctx->ne * 2.0 * s * (double)nb * nb; }
+double lu_flops(dg_ctx* ctx, int nb) { return ctx->ne * (2.0 / 3.0) * (double)nb * nb * nb; }
+
 void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* o) {
     check_pmg_opts(ctx, o);
     ctx->pmg_ready = false;
@@ -293,7 +331,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     dot(ctx, ctx->W0.p, ctx->W0.p, N, sc(ctx, S_PMG_NW2));
     const int nb = ctx->nb;
     ctx->blk.ensure((size_t)ctx->ne * nb * nb);
-    CK(launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->s));
+    timed(ctx, DG_K_DIAG_BLOCKS, 8.0 * ctx->ne * (double)nb * nb + 8.0 * (double)ctx->N, 0.0, [&] { return launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->s); });
     for (size_t l = o->n_levels; l < ctx->lv.size(); ++l) ctx->lv[l].release();
     ctx->lv.resize(o->n_levels);
     for (int l = 0; l < o->n_levels; ++l) {
@@ -304,6 +342,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         L.ndof = (size_t)ctx->ne * L.nb;
         L.use32 = (l == 0) ? (o->prec_fine == DG_FP32) : (o->prec_coarse == DG_FP32);
         L.piv.ensure((size_t)ctx->ne * L.nb);
+        L.pos.ensure((size_t)ctx->ne * L.nb);
         L.x.ensure(L.ndof);
         L.b.ensure(L.ndof);
         L.r.ensure(L.ndof);
@@ -318,14 +357,14 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
             L.f32.ensure(sz);
             if (l == 0) CK(launch_convert_fp64_to_fp32(ctx->blk.p, L.f32.p, sz, ctx->s));
             else CK(launch_extract_sub<float>(ctx->blk.p, nb, ctx->nv, L.nv, L.f32.p, ctx->ne, ctx->s));
-            CK(launch_lu<float>(L.f32.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+            timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 4.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<float>(L.f32.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
         } else {
             if (l == 0) {
-                CK(launch_lu<double>(ctx->blk.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(ctx->blk.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
             } else {
                 L.f64.ensure(sz);
                 CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, L.f64.p, ctx->ne, ctx->s));
-                CK(launch_lu<double>(L.f64.p, L.piv.p, ctx->ne, L.nb, ctx->s));
+                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(L.f64.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
             }
         }
     }
@@ -353,7 +392,7 @@ void fgmres_impl(dg_ctx* ctx, const double* W, const double* RW, const double* b
     fgmres_stats loc{};
     const double shift = ctx->pmg_ready ? ctx->shift : 0.0;
     auto op = [&](const double* v, double* y) {
-        if (o->jvp_exact) CK(launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s));
+        if (o->jvp_exact) timed(ctx, DG_K_JVP_EXACT, 24.0 * (double)ctx->N, 0.0, [&] { return launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s); });
         else jvp_fd(ctx, W, RW, v, shift, y, sc(ctx, S_F_NW2));
     };
     if (!o->jvp_exact) dot(ctx, W, W, n, sc(ctx, S_F_NW2));
@@ -439,7 +478,7 @@ void bdf2_impl(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, con
     dot(ctx, ctx->tmp1.p, ctx->tmp1.p, n, sc(ctx, S_N_M2));
     const double floor = 1e-14 * a * std::sqrt(read_scalar(ctx, sc(ctx, S_N_M2)));
     auto unsteady = [&]() -> double {
-        CK(launch_residual(ctx->a, W, ctx->RW.p, ctx->s));
+        timed(ctx, DG_K_RESIDUAL, 16.0 * (double)ctx->N, 0.0, [&] { return launch_residual(ctx->a, W, ctx->RW.p, ctx->s); });
         // t = 3 W - 4 Wn + Wnm1 ; Ru = M t / (2 dt) + RW
         CK(launch_axpby(n, 3.0, W, -4.0, Wn, ctx->tmp1.p, ctx->s));
         CK(launch_axpby(n, 1.0, Wnm1, 1.0, ctx->tmp1.p, ctx->tmp1.p, ctx->s));
@@ -607,6 +646,7 @@ dg_status dg_destroy(dg_ctx* ctx) {
     if (!ctx) return DG_EINVAL;
     if (ctx->s) (void)hipStreamSynchronize(ctx->s);
     else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
     ctx->vtx.release(); ctx->partial.release(); ctx->scal.release(); ctx->flag.release();
     ctx->tmp1.release(); ctx->tmp2.release(); ctx->tmp3.release();
     ctx->W0.release(); ctx->RW0.release(); ctx->blk.release();
@@ -644,7 +684,7 @@ dg_status dg_residual(dg_ctx* ctx, const double* W, double* R) {
         need(ctx, W, "W");
         need(ctx, R, "R");
         no_alias(ctx, R, W, "R/W");
-        CK(launch_residual(ctx->a, W, R, ctx->s));
+        timed(ctx, DG_K_RESIDUAL, 16.0 * (double)ctx->N, 0.0, [&] { return launch_residual(ctx->a, W, R, ctx->s); });
     });
 }
 
@@ -668,7 +708,7 @@ dg_status dg_jvp_exact(dg_ctx* ctx, const double* W, const double* v, double shi
         need(ctx, y, "y");
         no_alias(ctx, y, W, "y/W");
         no_alias(ctx, y, v, "y/v");
-        CK(launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s));
+        timed(ctx, DG_K_JVP_EXACT, 24.0 * (double)ctx->N, 0.0, [&] { return launch_jvp_exact(ctx->a, W, v, shift, y, ctx->s); });
     });
 }
 
@@ -690,8 +730,8 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
 }
 
 dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n) {
-    if (!A || !piv || nblk < 0 || n < 1 || n > 4096) return DG_EINVAL;
-    if (launch_lu<double>(A, piv, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
+    if (!A || !piv || nblk < 0 || n < 1 || n > 625) return DG_EINVAL;
+    if (launch_lu_blocked<double>(A, piv, nullptr, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
     return DG_OK;
 }
 
@@ -740,6 +780,38 @@ dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double
         no_alias(ctx, Wnp1, Wn, "Wnp1/Wn");
         no_alias(ctx, Wnp1, Wnm1, "Wnp1/Wnm1");
         bdf2_impl(ctx, Wn, Wnm1, dt, popts, fopts, newton_rtol, max_newton, Wnp1, stats);
+    });
+}
+
+dg_status dg_timing(dg_ctx* ctx, int enable) {
+    return guarded(ctx, [&] {
+        ctx->timing = enable != 0;
+        ctx->ev_used = 0;
+    });
+}
+
+dg_status dg_timing_read(dg_ctx* ctx, double* ms, int* counts, double* bytes, double* flops) {
+    return guarded(ctx, [&] {
+        need(ctx, ms, "ms");
+        need(ctx, counts, "counts");
+        need(ctx, bytes, "bytes");
+        need(ctx, flops, "flops");
+        CK(hipStreamSynchronize(ctx->s));
+        for (int k = 0; k < DG_K_COUNT; ++k) {
+            ms[k] = 0.0;
+            counts[k] = 0;
+            bytes[k] = 0.0;
+            flops[k] = 0.0;
+        }
+        for (size_t i = 0; i < ctx->ev_used; ++i) {
+            float t = 0.0f;
+            CK(hipEventElapsedTime(&t, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+            ms[ctx->ev_kind[i]] += t;
+            counts[ctx->ev_kind[i]] += 1;
+            bytes[ctx->ev_kind[i]] += ctx->ev_bytes[i];
+            flops[ctx->ev_kind[i]] += ctx->ev_flops[i];
+        }
+        ctx->ev_used = 0;
     });
 }
 

@@ -100,6 +100,13 @@ hipError_t launch_lu(TF* A, int* piv, int nblk, int n, hipStream_t s);
 template <class TF>
 hipError_t launch_lu_solve(const TF* LU, const int* piv, const double* r, double* z, int nblk, int n,
                            hipStream_t s);
+// Blocked PLU (same pivots) plus the gather index pos of the row permutation;
+// the blocked solve takes pos.  Dynamic LDS 2*16*n doubles (n <= 625).
+template <class TF>
+hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s);
+template <class TF>
+hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
+                                   hipStream_t s);
 // Extract coarse principal sub-blocks (FP64 column-major fine blocks) and round to TF.
 template <class TF>
 hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);

@@ -60,13 +60,23 @@ __global__ void __launch_bounds__(RED_THREADS) sum_stage2(const double* __restri
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// The grid depends only on n (>= 2 entries per thread, at most RED_BLOCKS
+// blocks), so the summation order is a function of n alone.
+static int red_blocks(size_t n) {
+    size_t b = (n + (size_t)RED_THREADS * 2 - 1) / ((size_t)RED_THREADS * 2);
+    if (b < 1) b = 1;
+    if (b > (size_t)RED_BLOCKS) b = RED_BLOCKS;
+    return (int)b;
+}
+
 hipError_t launch_multi_dot(const double* X, size_t ldx, int nx, const double* y, size_t n, double* partial,
                             double* out, hipStream_t s) {
+    const int nbk = red_blocks(n);
     for (int k0 = 0; k0 < nx; k0 += KCH) {
         const int kn = (nx - k0 < KCH) ? nx - k0 : KCH;
-        hipLaunchKernelGGL(multi_dot_stage1, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, ldx, k0, kn, y, n, partial);
+        hipLaunchKernelGGL(multi_dot_stage1, dim3(nbk), dim3(RED_THREADS), 0, s, X, ldx, k0, kn, y, n, partial);
     }
-    hipLaunchKernelGGL(sum_stage2, dim3(nx), dim3(RED_THREADS), 0, s, partial, RED_BLOCKS, out);
+    hipLaunchKernelGGL(sum_stage2, dim3(nx), dim3(RED_THREADS), 0, s, partial, nbk, out);
     return hipGetLastError();
 }
 

@@ -152,4 +152,270 @@ hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF*
 template hipError_t launch_extract_sub<double>(const double*, int, int, int, double*, int, hipStream_t);
 template hipError_t launch_extract_sub<float>(const double*, int, int, int, float*, int, hipStream_t);
 
+// ---- blocked variants used by the smoother -------------------------------------------------
+// Right-looking PLU with LU_NB-column panels.  The panel (rows k0..n-1) is
+// factored in LDS (pivot search, row exchange, scaling, rank-1 updates), the
+// panel's row exchanges are applied to the other columns, U12 = L11^-1 A12 is
+// solved per column in registers and staged in LDS, and the trailing matrix
+// A22 -= L21 U12 is updated with 4x4 register tiles.  Pivots are the same
+// partial-pivoting choices as the unblocked kernel (max |a_ik|, lowest index on
+// ties); only the summation order of the trailing updates differs.
+constexpr int LU_NB = 16;
+
+template <class TF>
+__global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n) {
+    extern __shared__ double lds[];
+    double* P = lds;                      // panel, column-major with stride n: P[c*n + r], r < m
+    double* U = lds + (size_t)LU_NB * n;  // U12, LU_NB x (n - k0 - kb): U[t*n + c']
+    __shared__ double rv[LU_THREADS];
+    __shared__ int ri[LU_THREADS];
+    __shared__ int spiv[LU_NB];
+    TF* a = A + (size_t)blockIdx.x * n * n;
+    int* pv = piv + (size_t)blockIdx.x * n;
+    const int t = threadIdx.x;
+    for (int k0 = 0; k0 < n; k0 += LU_NB) {
+        const int kb = min(LU_NB, n - k0), m = n - k0;
+        for (int idx = t; idx < m * kb; idx += LU_THREADS) {
+            const int c = idx / m, r = idx % m;
+            P[c * n + r] = (double)a[(size_t)(k0 + c) * n + k0 + r];
+        }
+        __syncthreads();
+        for (int j = 0; j < kb; ++j) {
+            double best = -1.0;
+            int bi = m;
+            for (int r = j + t; r < m; r += LU_THREADS) {
+                const double v = fabs(P[j * n + r]);
+                if (v > best) { best = v; bi = r; }
+            }
+            rv[t] = best;
+            ri[t] = bi;
+            __syncthreads();
+            for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
+                if (t < s) {
+                    const double v2 = rv[t + s];
+                    const int i2 = ri[t + s];
+                    if (v2 > rv[t] || (v2 == rv[t] && i2 < ri[t])) { rv[t] = v2; ri[t] = i2; }
+                }
+                __syncthreads();
+            }
+            int p = ri[0];
+            if (p < j || p >= m) p = j;
+            if (t == 0) {
+                spiv[j] = p;
+                pv[k0 + j] = k0 + p;
+            }
+            if (p != j && t < kb) {
+                const double x = P[t * n + j];
+                P[t * n + j] = P[t * n + p];
+                P[t * n + p] = x;
+            }
+            __syncthreads();
+            const double inv = 1.0 / P[j * n + j];
+            for (int r = j + 1 + t; r < m; r += LU_THREADS) {
+                const double l = P[j * n + r] * inv;
+                P[j * n + r] = l;
+                for (int c = j + 1; c < kb; ++c) P[c * n + r] -= l * P[c * n + j];
+            }
+            __syncthreads();
+        }
+        // panel back to memory (rounded to the storage type)
+        for (int idx = t; idx < m * kb; idx += LU_THREADS) {
+            const int c = idx / m, r = idx % m;
+            a[(size_t)(k0 + c) * n + k0 + r] = (TF)P[c * n + r];
+        }
+        // row exchanges of this panel applied to the columns left and right of it
+        for (int j = 0; j < kb; ++j) {
+            const int p = spiv[j];
+            if (p != j)
+                for (int c = t; c < n; c += LU_THREADS) {
+                    if (c >= k0 && c < k0 + kb) continue;
+                    const TF x = a[(size_t)c * n + k0 + j];
+                    a[(size_t)c * n + k0 + j] = a[(size_t)c * n + k0 + p];
+                    a[(size_t)c * n + k0 + p] = x;
+                }
+            __syncthreads();
+        }
+        const int n2 = n - k0 - kb;
+        if (n2 <= 0) break;
+        // U12 = L11^-1 A12, one column per thread, staged in LDS
+        for (int c = t; c < n2; c += LU_THREADS) {
+            double x[LU_NB];
+#pragma unroll
+            for (int i = 0; i < LU_NB; ++i) x[i] = (i < kb) ? (double)a[(size_t)(k0 + kb + c) * n + k0 + i] : 0.0;
+#pragma unroll
+            for (int i = 1; i < LU_NB; ++i)
+#pragma unroll
+                for (int q = 0; q < i; ++q)
+                    if (i < kb) x[i] -= P[q * n + i] * x[q];
+#pragma unroll
+            for (int i = 0; i < LU_NB; ++i)
+                if (i < kb) {
+                    a[(size_t)(k0 + kb + c) * n + k0 + i] = (TF)x[i];
+                    U[i * n + c] = x[i];
+                }
+        }
+        __syncthreads();
+        // A22 -= L21 U12 with 4x4 tiles
+        const int tr = (n2 + 3) / 4;
+        const int ntile = tr * tr;
+        for (int tile = t; tile < ntile; tile += LU_THREADS) {
+            const int r0 = (tile % tr) * 4, c0 = (tile / tr) * 4;
+            double acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+            for (int q = 0; q < kb; ++q) {
+                double lv[4], uv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < n2) ? P[q * n + kb + r0 + i] : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? U[q * n + c0 + jj] : 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(lv[i], uv[jj], acc[i][jj]);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if (c0 + jj >= n2) continue;
+                TF* colp = a + (size_t)(k0 + kb + c0 + jj) * n + k0 + kb + r0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (r0 + i < n2) colp[i] = (TF)((double)colp[i] - acc[i][jj]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// pos[i] such that (P b)[i] = b[pos[i]] for the exchanges recorded in piv.
+__global__ void __launch_bounds__(256) lu_pos_kernel(const int* __restrict__ piv, int* __restrict__ pos, int n) {
+    extern __shared__ int sp[];
+    const int* pv = piv + (size_t)blockIdx.x * n;
+    int* po = pos + (size_t)blockIdx.x * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sp[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < n; ++k) {
+            const int p = pv[k];
+            if (p > k && p < n) {
+                const int x = sp[k];
+                sp[k] = sp[p];
+                sp[p] = x;
+            }
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) po[i] = sp[i];
+}
+
+// z = U^-1 L^-1 P r with TS-wide panels, one wavefront per element block:
+// the TS x TS diagonal triangle is solved with cross-lane shuffles (each lane
+// preloads its triangle row), the rows beyond it are updated by all lanes
+// (coalesced reads of the factor columns).  With one wavefront per block all
+// element blocks of a CU are resident together, so the sequential panel chain
+// of one block overlaps with the factor streams of the others.
+constexpr int TS = 32;
+constexpr int SOLVE_THREADS = 64;
+
+template <class TF>
+__global__ void __launch_bounds__(SOLVE_THREADS)
+    lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
+                            double* __restrict__ z, int n) {
+    extern __shared__ double x[];
+    const TF* a = LU + (size_t)blockIdx.x * n * n;
+    const int* po = pos + (size_t)blockIdx.x * n;
+    const double* rb = r + (size_t)blockIdx.x * n;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    for (int i = t; i < n; i += SOLVE_THREADS) x[i] = rb[po[i]];
+    __syncthreads();
+    // forward, unit lower
+    for (int k0 = 0; k0 < n; k0 += TS) {
+        const int kb = min(TS, n - k0);
+        {
+            // lane i holds row i of the diagonal triangle (loads issued together)
+            double lrow[TS];
+#pragma unroll
+            for (int j = 0; j < TS; ++j)
+                lrow[j] = (j < kb && lane < kb && lane > j) ? (double)a[(size_t)(k0 + j) * n + k0 + lane] : 0.0;
+            double xi = (lane < kb) ? x[k0 + lane] : 0.0;
+#pragma unroll
+            for (int j = 0; j < TS - 1; ++j) {
+                const double xj = __shfl(xi, j, 64);
+                xi -= lrow[j] * xj;
+            }
+            if (lane < kb) x[k0 + lane] = xi;
+        }
+        __syncthreads();
+        for (int row = k0 + kb + t; row < n; row += SOLVE_THREADS) {
+            double acc = x[row];
+            for (int j = 0; j < kb; ++j) acc -= (double)a[(size_t)(k0 + j) * n + row] * x[k0 + j];
+            x[row] = acc;
+        }
+        __syncthreads();
+    }
+    // backward, upper
+    const int nb0 = ((n - 1) / TS) * TS;
+    for (int k0 = nb0; k0 >= 0; k0 -= TS) {
+        const int kb = min(TS, n - k0);
+        {
+            double urow[TS];
+#pragma unroll
+            for (int j = 0; j < TS; ++j)
+                urow[j] = (j < kb && lane < kb && lane <= j) ? (double)a[(size_t)(k0 + j) * n + k0 + lane] : 0.0;
+            double xi = (lane < kb) ? x[k0 + lane] : 0.0;
+#pragma unroll
+            for (int j = TS - 1; j >= 0; --j) {
+                if (j < kb) {
+                    if (lane == j) xi /= urow[j];
+                    const double xj = __shfl(xi, j, 64);
+                    if (lane < j) xi -= urow[j] * xj;
+                }
+            }
+            if (lane < kb) x[k0 + lane] = xi;
+        }
+        __syncthreads();
+        for (int row = t; row < k0; row += SOLVE_THREADS) {
+            double acc = x[row];
+            for (int j = 0; j < kb; ++j) acc -= (double)a[(size_t)(k0 + j) * n + row] * x[k0 + j];
+            x[row] = acc;
+        }
+        __syncthreads();
+    }
+    double* zb = z + (size_t)blockIdx.x * n;
+    for (int i = t; i < n; i += SOLVE_THREADS) zb[i] = x[i];
+}
+
+size_t lu_blocked_lds(int n) { return (size_t)2 * LU_NB * n * sizeof(double); }
+
+template <class TF>
+hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    const size_t lds = lu_blocked_lds(n);
+    hipError_t e = hipFuncSetAttribute((const void*)lu_blocked_kernel<TF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lu_blocked_kernel<TF>, dim3(nblk), dim3(LU_THREADS), lds, s, A, piv, n);
+    e = hipGetLastError();
+    if (e != hipSuccess || !pos) return e;
+    hipLaunchKernelGGL(lu_pos_kernel, dim3(nblk), dim3(256), n * sizeof(int), s, piv, pos, n);
+    return hipGetLastError();
+}
+template hipError_t launch_lu_blocked<double>(double*, int*, int*, int, int, hipStream_t);
+template hipError_t launch_lu_blocked<float>(float*, int*, int*, int, int, hipStream_t);
+
+template <class TF>
+hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
+                                   hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lu_solve_blocked_kernel<TF>, dim3(nblk), dim3(SOLVE_THREADS), n * sizeof(double), s, LU, pos,
+                       r, z, n);
+    return hipGetLastError();
+}
+template hipError_t launch_lu_solve_blocked<double>(const double*, const int*, const double*, double*, int, int,
+                                                    hipStream_t);
+template hipError_t launch_lu_solve_blocked<float>(const float*, const int*, const double*, double*, int, int,
+                                                   hipStream_t);
+
 }  // namespace dg
