@@ -81,11 +81,17 @@ typedef struct {
  *  nu_pre/nu_post damped block-Jacobi sweeps x += omega D^-1 (b - K x) per level.
  *  coarsest_iters right-preconditioned GMRES(BJ) iterations on the coarsest level.
  *  prec_fine      DG_FP64 or DG_FP32: storage/arithmetic of the level-0 PLU factors.
- *  prec_coarse    DG_FP64, DG_FP32 or DG_BF16: storage of coarse blocks and factors
- *                 (FP32 accumulation for BF16).
- *  coarse_matrix_free  0: assembled inherited coarse blocks (diagonal + 6 face
- *                 neighbours, block-sparse);  1: coarse products applied as
- *                 P^T K_0 P through the fine exact Jacobian action. */
+ *  prec_coarse    DG_FP64, DG_FP32 or DG_BF16: storage of the assembled coarse
+ *                 operator blocks (BF16: rounded to nearest even, products
+ *                 accumulated in FP32); coarse block-Jacobi factors are FP64
+ *                 for DG_FP64 and FP32 otherwise.
+ *  coarse_matrix_free  how the inherited coarse operators K_l = P^T K_0 P
+ *                 (Sec. 6.1) are applied: 0 = assembled for every coarse level
+ *                 (diagonal + 6 face-coupling blocks per element, block-sparse
+ *                 product); 1 = matrix-free for every coarse level (the
+ *                 level-0 finite-difference product of Eq. DG-mf on the
+ *                 zero-padded vector, then restricted); 2 = assembled on the
+ *                 coarsest level only, matrix-free above it. */
 typedef struct {
     int n_levels;
     int p_level[4];
@@ -157,6 +163,14 @@ dg_status dg_mass(dg_ctx* ctx, const double* v, double* y);
  * i = equation * (p+1)^3 + mode. */
 dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* blocks);
 
+/* Face-coupling blocks of the inherited coarse operator of degree pc
+ * (Sec. 6.1, K_l = P^T K_0 P; 1 <= pc < p): off [ne][6][nbc][nbc], nbc =
+ * 5 (pc+1)^3, column-major, off[e][f][j][i] = dR_{e,i}/dW_{nb(e,f),j} through
+ * the integral over face f only (i, j equation-major over the modes of
+ * degree <= pc).  A face whose neighbour is the element itself gives a zero
+ * block (that coupling is part of the diagonal block). */
+dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off);
+
 /* Batched PLU with partial pivoting (Sec. 6.3), in place, LAPACK convention
  * (column-major blocks, rows k and piv[k] exchanged at step k, unit-lower L
  * below the diagonal).  A device [nblk][n][n], piv device int [nblk][n],
@@ -193,6 +207,12 @@ dg_status fgmres_step(dg_ctx* ctx, const double* W, const double* RW, const doub
 dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
                        const fgmres_opts* fopts, double newton_rtol, int max_newton, double* Wnp1,
                        dg_step_stats* stats);
+
+/* pmg_apply replays the V-cycle as a HIP graph captured after each
+ * pmg_setup (enabled by default; the launch sequence of a V-cycle is fixed
+ * by the setup).  enable = 0 runs every launch eagerly on the context stream.
+ * Graph replay is skipped while per-kernel timing is enabled. */
+dg_status dg_use_graphs(dg_ctx* ctx, int enable);
 
 /* Per-kernel timing (instrumentation for measurement): while enabled, every
  * launch of the listed kernel families on the context's stream is bracketed

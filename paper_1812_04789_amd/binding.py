@@ -67,11 +67,13 @@ SIGNATURES = {
     "dg_jvp_exact": (_I, [_P, _P, _P, _D, _P]),
     "dg_mass": (_I, [_P, _P, _P]),
     "dg_assemble_diag": (_I, [_P, _P, _D, _P]),
+    "dg_assemble_coarse": (_I, [_P, _P, _I, _P]),
     "dg_batched_lu": (_I, [_P, _P, _P, _I, _I]),
     "dg_batched_lu_solve": (_I, [_P, _P, _P, _P, _P, _I, _I]),
     "pmg_setup": (_I, [_P, _P, _D, ctypes.POINTER(PmgOpts)]),
     "pmg_apply": (_I, [_P, _P, _P]),
     "fgmres_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(FgmresOpts), ctypes.POINTER(FgmresStats)]),
+    "dg_use_graphs": (_I, [_P, _I]),
     "dg_timing": (_I, [_P, _I]),
     "dg_timing_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "dg_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
@@ -228,6 +230,12 @@ class Context:
         self._check(self.lib.dg_assemble_diag(self.h, self._vec(W, "W"), float(shift), _ptr(out)))
         return out.view(self.ne, nb, nb)       # [e][col][row]
 
+    def assemble_coarse(self, W, pc):
+        nbc = 5 * (pc + 1) ** 3
+        out = self.empty(self.ne * 6 * nbc * nbc)
+        self._check(self.lib.dg_assemble_coarse(self.h, self._vec(W, "W"), int(pc), _ptr(out)))
+        return out.view(self.ne, 6, nbc, nbc)     # [e][f][col][row]
+
     def pmg_setup(self, W, shift, opts):
         self._check(self.lib.pmg_setup(self.h, self._vec(W, "W"), float(shift), ctypes.byref(opts)))
 
@@ -244,6 +252,9 @@ class Context:
         if s != DG_OK and (raise_on_noconv or s != DG_ENOCONV):
             self._check(s)
         return x, st
+
+    def use_graphs(self, enable):
+        self._check(self.lib.dg_use_graphs(self.h, 1 if enable else 0))
 
     def timing(self, enable):
         self._check(self.lib.dg_timing(self.h, 1 if enable else 0))

@@ -87,7 +87,14 @@ struct Level {
     DBuf<int> piv, pos;
     bool use32 = false;
     DBuf<double> x, b, r, t, z;
-    void release() { f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
+    // assembled inherited operator: diagonal + 6 face blocks per element
+    bool assembled = false;
+    int op_prec = DG_FP64;
+    DBuf<double> od64, oo64;
+    DBuf<float> od32, oo32;
+    DBuf<unsigned short> od16, oo16;
+    void release() { od64.release(); oo64.release(); od32.release(); oo32.release(); od16.release(); oo16.release();
+                     f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
 };
 
 std::mutex g_tab_mu;
@@ -113,12 +120,17 @@ struct dg_ctx {
     bool pmg_ready = false;
     pmg_opts popt{};
     double shift = 0.0;
-    DBuf<double> W0, RW0, blk;
+    DBuf<double> W0, RW0, blk, otmp, dtmp;
     std::vector<Level> lv;
     Krylov kc;                              // coarsest-level GMRES
     Krylov kf;                              // outer FGMRES
     // Newton
     DBuf<double> RW, Ru, xN;
+    // V-cycle replayed as a HIP graph (captured on a private stream after setup)
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t vc_exec = nullptr;
+    DBuf<double> gin, gout;
     // per-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;          // pairs (start, stop)
@@ -216,6 +228,15 @@ void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
         return;
     }
     const Level& L = ctx->lv[l];
+    if (L.assembled) {
+        const double nbc = L.nb, sz = L.op_prec == DG_FP64 ? 8.0 : (L.op_prec == DG_FP32 ? 4.0 : 2.0);
+        timed(ctx, DG_K_BSR, ctx->ne * (7.0 * nbc * nbc * sz + 16.0 * nbc), ctx->ne * 14.0 * nbc * nbc, [&] {
+            if (L.op_prec == DG_FP64) return launch_bsr7<double>(ctx->a, L.od64.p, L.oo64.p, x, y, L.nb, ctx->s);
+            if (L.op_prec == DG_FP32) return launch_bsr7<float>(ctx->a, L.od32.p, L.oo32.p, x, y, L.nb, ctx->s);
+            return launch_bsr7<unsigned short>(ctx->a, L.od16.p, L.oo16.p, x, y, L.nb, ctx->s);
+        });
+        return;
+    }
     CK(launch_prolong_add(ctx->ne, ctx->nv, L.nv, x, ctx->tmp1.p, 1, ctx->s));
     jvp_fd(ctx, ctx->W0.p, ctx->RW0.p, ctx->tmp1.p, ctx->shift, ctx->tmp2.p, sc(ctx, S_PMG_NW2));
     CK(launch_restrict(ctx->ne, ctx->nv, L.nv, ctx->tmp2.p, y, ctx->s));
@@ -290,13 +311,54 @@ void vcycle(dg_ctx* ctx, int l, const double* b, double* x) {
     smooth(ctx, l, x, b, ctx->popt.nu_post, false);
 }
 
+void drop_graph(dg_ctx* ctx) {
+    if (ctx->vc_exec) (void)hipGraphExecDestroy(ctx->vc_exec);
+    ctx->vc_exec = nullptr;
+}
+
+void pmg_apply_eager(dg_ctx* ctx, const double* r, double* z) {
+    if (ctx->lv.size() == 1) bj_apply(ctx, 0, r, z);
+    else vcycle(ctx, 0, r, z);
+}
+
+// Capture one V-cycle from ctx->gin to ctx->gout.  The sequence of launches
+// depends only on the setup, so it is recorded once per pmg_setup.
+void capture_vcycle(dg_ctx* ctx) {
+    if (!ctx->cap_stream) CK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    ctx->gin.ensure(ctx->N);
+    ctx->gout.ensure(ctx->N);
+    hipStream_t saved = ctx->s;
+    ctx->s = ctx->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        try {
+            pmg_apply_eager(ctx, ctx->gin.p, ctx->gout.p);
+        } catch (...) {
+            (void)hipStreamEndCapture(ctx->cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            ctx->s = saved;
+            throw;
+        }
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+    }
+    ctx->s = saved;
+    CK(e);
+    e = hipGraphInstantiate(&ctx->vc_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CK(e);
+}
+
 void pmg_apply_impl(dg_ctx* ctx, const double* r, double* z) {
     if (!ctx->pmg_ready) fail(ctx, DG_ESTATE, "pmg_apply before pmg_setup");
-    if (ctx->lv.size() == 1) {
-        bj_apply(ctx, 0, r, z);
+    if (!ctx->use_graphs || ctx->timing) {
+        pmg_apply_eager(ctx, r, z);
         return;
     }
-    vcycle(ctx, 0, r, z);
+    if (!ctx->vc_exec) capture_vcycle(ctx);
+    CK(launch_copy(ctx->N, r, ctx->gin.p, ctx->s));
+    CK(hipGraphLaunch(ctx->vc_exec, ctx->s));
+    CK(launch_copy(ctx->N, ctx->gout.p, z, ctx->s));
 }
 
 void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
@@ -309,10 +371,9 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
     if (o->nu_pre < 0 || o->nu_post < 0 || o->coarsest_iters < 1 || o->coarsest_iters > 200)
         fail(ctx, DG_EINVAL, "bad sweep or coarsest iteration counts");
     if (o->prec_fine != DG_FP64 && o->prec_fine != DG_FP32) fail(ctx, DG_EINVAL, "prec_fine must be FP64 or FP32");
-    if (o->prec_coarse != DG_FP64 && o->prec_coarse != DG_FP32)
-        fail(ctx, DG_EINVAL, "prec_coarse must be FP64 or FP32");
-    if (!o->coarse_matrix_free && o->n_levels > 1)
-        fail(ctx, DG_EINVAL, "assembled coarse operators are not available in this build");
+    if (o->prec_coarse != DG_FP64 && o->prec_coarse != DG_FP32 && o->prec_coarse != DG_BF16)
+        fail(ctx, DG_EINVAL, "prec_coarse must be FP64, FP32 or BF16");
+    if (o->coarse_matrix_free < 0 || o->coarse_matrix_free > 2) fail(ctx, DG_EINVAL, "coarse_matrix_free must be 0, 1 or 2");
 }
 
 double lu_bytes(dg_ctx* ctx, int nb, double s) { return ctx->ne * 2.0 * s * (double)nb * nb; }
@@ -321,6 +382,7 @@ double lu_flops(dg_ctx* ctx, int nb) { return ctx->ne * (2.0 / 3.0) * (double)nb
 void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* o) {
     check_pmg_opts(ctx, o);
     ctx->pmg_ready = false;
+    drop_graph(ctx);
     ctx->popt = *o;
     ctx->shift = shift;
     const size_t N = ctx->N;
@@ -340,7 +402,10 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         L.nv = (L.p + 1) * (L.p + 1) * (L.p + 1);
         L.nb = 5 * L.nv;
         L.ndof = (size_t)ctx->ne * L.nb;
-        L.use32 = (l == 0) ? (o->prec_fine == DG_FP32) : (o->prec_coarse == DG_FP32);
+        L.use32 = (l == 0) ? (o->prec_fine == DG_FP32) : (o->prec_coarse != DG_FP64);
+        L.assembled = l > 0 && (o->coarse_matrix_free == 0 ||
+                                (o->coarse_matrix_free == 2 && l == o->n_levels - 1));
+        L.op_prec = o->prec_coarse;
         L.piv.ensure((size_t)ctx->ne * L.nb);
         L.pos.ensure((size_t)ctx->ne * L.nb);
         L.x.ensure(L.ndof);
@@ -353,6 +418,29 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     for (int l = o->n_levels - 1; l >= 0; --l) {
         Level& L = ctx->lv[l];
         const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
+        if (L.assembled) {
+            // inherited operator K_l = P^T K_0 P: diagonal sub-blocks + face-coupling blocks
+            ctx->dtmp.ensure(sz);
+            ctx->otmp.ensure(6 * sz);
+            CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
+            CK(launch_offdiag_blocks(ctx->a, ctx->W0.p, L.p, ctx->otmp.p, ctx->s));
+            if (L.op_prec == DG_FP64) {
+                L.od64.ensure(sz);
+                L.oo64.ensure(6 * sz);
+                CK(launch_copy(sz, ctx->dtmp.p, L.od64.p, ctx->s));
+                CK(launch_copy(6 * sz, ctx->otmp.p, L.oo64.p, ctx->s));
+            } else if (L.op_prec == DG_FP32) {
+                L.od32.ensure(sz);
+                L.oo32.ensure(6 * sz);
+                CK(launch_convert_fp64_to_fp32(ctx->dtmp.p, L.od32.p, sz, ctx->s));
+                CK(launch_convert_fp64_to_fp32(ctx->otmp.p, L.oo32.p, 6 * sz, ctx->s));
+            } else {
+                L.od16.ensure(sz);
+                L.oo16.ensure(6 * sz);
+                CK(launch_convert_fp64_to_bf16(ctx->dtmp.p, L.od16.p, sz, ctx->s));
+                CK(launch_convert_fp64_to_bf16(ctx->otmp.p, L.oo16.p, 6 * sz, ctx->s));
+            }
+        }
         if (L.use32) {
             L.f32.ensure(sz);
             if (l == 0) CK(launch_convert_fp64_to_fp32(ctx->blk.p, L.f32.p, sz, ctx->s));
@@ -647,9 +735,13 @@ dg_status dg_destroy(dg_ctx* ctx) {
     if (ctx->s) (void)hipStreamSynchronize(ctx->s);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    ctx->gin.release();
+    ctx->gout.release();
     ctx->vtx.release(); ctx->partial.release(); ctx->scal.release(); ctx->flag.release();
     ctx->tmp1.release(); ctx->tmp2.release(); ctx->tmp3.release();
-    ctx->W0.release(); ctx->RW0.release(); ctx->blk.release();
+    ctx->W0.release(); ctx->RW0.release(); ctx->blk.release(); ctx->otmp.release(); ctx->dtmp.release();
     for (auto& L : ctx->lv) L.release();
     ctx->kc.release(); ctx->kf.release();
     ctx->RW.release(); ctx->Ru.release(); ctx->xN.release();
@@ -729,6 +821,15 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
     });
 }
 
+dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, off, "off");
+        if (pc < 1 || pc >= ctx->p) fail(ctx, DG_EINVAL, "pc must satisfy 1 <= pc < p");
+        CK(launch_offdiag_blocks(ctx->a, W, pc, off, ctx->s));
+    });
+}
+
 dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n) {
     if (!A || !piv || nblk < 0 || n < 1 || n > 625) return DG_EINVAL;
     if (launch_lu_blocked<double>(A, piv, nullptr, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
@@ -780,6 +881,13 @@ dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double
         no_alias(ctx, Wnp1, Wn, "Wnp1/Wn");
         no_alias(ctx, Wnp1, Wnm1, "Wnp1/Wnm1");
         bdf2_impl(ctx, Wn, Wnm1, dt, popts, fopts, newton_rtol, max_newton, Wnp1, stats);
+    });
+}
+
+dg_status dg_use_graphs(dg_ctx* ctx, int enable) {
+    return guarded(ctx, [&] {
+        ctx->use_graphs = enable != 0;
+        if (!ctx->use_graphs) drop_graph(ctx);
     });
 }
 

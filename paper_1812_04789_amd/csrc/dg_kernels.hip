@@ -156,6 +156,58 @@ __device__ __forceinline__ T load_state(const double* W, const double* v, double
     }
 }
 
+// Face integrand at one face point, seen from the + element: the Roe flux and
+// the BR2 viscous flux (Eq. visc_flux with the closed-form lifting
+// delta = lambda G) times the face weight, and the adjoint-consistency
+// (symmetry) term mapped to reference gradients.  out[0..4] multiplies
+// phi_i, out[5 + 3a + k] multiplies dphi_i/dxi_k (both summed onto R_+).
+//   up, gxp: + trace and its reference gradient; um, gxm: - trace;
+//   nrm: unit normal out of +;  Jip/Jim: dxi/dx on each side;
+//   lam_p/lam_m: BR2 lifting factors;  sc = w_face * J_F.
+template <class T, bool NS>
+__device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3], const T um[5], const T gxm[5][3],
+                                               const double nrm[3], const double Jip[3][3], const double Jim[3][3],
+                                               double lam_p, double lam_m, double sc, const Gas& gas, T* fo) {
+    T Fh[5];
+    roe_flux(up, um, nrm, gas.gamma, Fh);
+    if constexpr (NS) {
+        T gp[5][3], gm[5][3], X[5][3];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const T jmp = up[a] - um[a];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                gp[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
+                gm[a][j] = Jim[0][j] * gxm[a][0] + Jim[1][j] * gxm[a][1] + Jim[2][j] * gxm[a][2];
+                X[a][j] = jmp * nrm[j];
+            }
+        }
+        T Fv[5][3], Gp[5][3], Gm[5][3];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Fv[a][j] = Gp[a][j] = Gm[a][j] = 0.0;
+        flux_v_acc(up, gp, gas, 0.5, Fv);
+        flux_v_acc(um, gm, gas, 0.5, Fv);
+        flux_v_acc(up, X, gas, -0.5, Gp);     // G+ = 1/2 K(u+)(n+ (x) [u]) = -1/2 F_v(u+, [u] (x) n+)
+        flux_v_acc(um, X, gas, -0.5, Gm);
+        const double cp = 0.5 * gas.eta * lam_p, cm = 0.5 * gas.eta * lam_m;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            T fn = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) fn = fn + (Fv[a][j] + cp * Gp[a][j] + cm * Gm[a][j]) * nrm[j];
+            fo[a] = sc * (Fh[a] + fn);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                fo[5 + a * 3 + k] = -sc * (Jip[k][0] * Gp[a][0] + Jip[k][1] * Gp[a][1] + Jip[k][2] * Gp[a][2]);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) fo[a] = sc * Fh[a];
+    }
+}
+
 template <int P, bool NS, bool CURVED, int MODE>
 __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ))
     dg_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ V,
@@ -419,46 +471,8 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
                     for (int dd = 0; dd < 3; ++dd) Jim[k][dd] = Jip[k][dd];
                 lam_p = lam_m = 0.5 * N * N * JF / detJ;
             }
-            const double sc = tb.w[qt1] * tb.w[qt2] * JF;
-            T Fh[5];
-            roe_flux(up, um, nrm, gas.gamma, Fh);
-            T* fo = sF + (f * NF + fq) * 20;
-            if constexpr (NS) {
-                T gp[5][3], gm[5][3], X[5][3];
-#pragma unroll
-                for (int a = 0; a < 5; ++a) {
-                    const T jmp = up[a] - um[a];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        gp[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
-                        gm[a][j] = Jim[0][j] * gxm[a][0] + Jim[1][j] * gxm[a][1] + Jim[2][j] * gxm[a][2];
-                        X[a][j] = jmp * nrm[j];
-                    }
-                }
-                T Fv[5][3], Gp[5][3], Gm[5][3];
-#pragma unroll
-                for (int a = 0; a < 5; ++a)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) Fv[a][j] = Gp[a][j] = Gm[a][j] = 0.0;
-                flux_v_acc(up, gp, gas, 0.5, Fv);
-                flux_v_acc(um, gm, gas, 0.5, Fv);
-                flux_v_acc(up, X, gas, -0.5, Gp);     // G+ = 1/2 K(u+)(n+ (x) [u]) = -1/2 F_v(u+, [u] (x) n+)
-                flux_v_acc(um, X, gas, -0.5, Gm);
-                const double cp = 0.5 * gas.eta * lam_p, cm = 0.5 * gas.eta * lam_m;
-#pragma unroll
-                for (int a = 0; a < 5; ++a) {
-                    T fn = 0.0;
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) fn = fn + (Fv[a][j] + cp * Gp[a][j] + cm * Gm[a][j]) * nrm[j];
-                    fo[a] = sc * (Fh[a] + fn);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        fo[5 + a * 3 + k] = -sc * (Jip[k][0] * Gp[a][0] + Jip[k][1] * Gp[a][1] + Jip[k][2] * Gp[a][2]);
-                }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 5; ++a) fo[a] = sc * Fh[a];
-            }
+            face_integrand<T, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
+                                  sF + (f * NF + fq) * 20);
         }
     }
     __syncthreads();
@@ -825,5 +839,291 @@ hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+// ---- inherited coarse operators (Sec. 6.1) ---------------------------------------------------
+// Geometry of face point (qt1, qt2) of face f of element e seen from both
+// sides, everything from the vertex tables (curved) or the box spacing.
+template <int P, bool CURVED>
+__device__ __forceinline__ void face_geometry(const Tab& tb, const MeshDev& m, int e, int f, int qt1, int qt2,
+                                              double nrm[3], double& JF, double Jip[3][3], double Jim[3][3],
+                                              double& lam_p, double& lam_m) {
+    constexpr int N = P + 1;
+    const int d = f >> 1, s = f & 1;
+    const int t1 = (d == 0) ? 1 : 0;
+    const double sgn = s ? 1.0 : -1.0;
+    if constexpr (CURVED) {
+        const double z1 = tb.z[qt1], z2 = tb.z[qt2];
+        const double* vo = m.vtx + (size_t)e * 24;
+        const double* vn = m.vtx + (size_t)nbr_of(m, e, f) * 24;
+        double xi[3], J[3][3];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
+        q1_jac(vo, xi[0], xi[1], xi[2], J);
+        q1_inv(J, Jip);
+        const int da = (d + 1) % 3, db = (d + 2) % 3;
+        double ta[3], tbv[3];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            ta[kk] = (da == 0) ? J[kk][0] : ((da == 1) ? J[kk][1] : J[kk][2]);
+            tbv[kk] = (db == 0) ? J[kk][0] : ((db == 1) ? J[kk][1] : J[kk][2]);
+        }
+        const double cx = ta[1] * tbv[2] - ta[2] * tbv[1];
+        const double cy = ta[2] * tbv[0] - ta[0] * tbv[2];
+        const double cz = ta[0] * tbv[1] - ta[1] * tbv[0];
+        JF = sqrt(cx * cx + cy * cy + cz * cz);
+        nrm[0] = sgn * cx / JF;
+        nrm[1] = sgn * cy / JF;
+        nrm[2] = sgn * cz / JF;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? -sgn : ((kk == t1) ? z1 : z2);
+        q1_jac(vn, xi[0], xi[1], xi[2], J);
+        q1_inv(J, Jim);
+        double sp = 0.0, sm = 0.0;
+        for (int k = 0; k < N; ++k) {
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
+            q1_jac(vo, xi[0], xi[1], xi[2], J);
+            sp += tb.br2[s][k] / q1_det(J);
+            q1_jac(vn, xi[0], xi[1], xi[2], J);
+            sm += tb.br2[1 - s][k] / q1_det(J);
+        }
+        lam_p = JF * sp;
+        lam_m = JF * sm;
+    } else {
+        const double hx = m.h[0], hy = m.h[1], hz = m.h[2];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) nrm[kk] = (kk == d) ? sgn : 0.0;
+        JF = 0.25 * ((d == 0) ? hy * hz : ((d == 1) ? hx * hz : hx * hy));
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) Jip[k][dd] = Jim[k][dd] = 0.0;
+        Jip[0][0] = Jim[0][0] = 2.0 / hx;
+        Jip[1][1] = Jim[1][1] = 2.0 / hy;
+        Jip[2][2] = Jim[2][2] = 2.0 / hz;
+        lam_p = lam_m = 0.5 * N * N * JF / (0.125 * hx * hy * hz);
+    }
+}
+
+// Basis function of tensor mode (i0,i1,i2) and its reference gradient at
+// the face point (qt1, qt2) of the face with normal direction d on end s.
+template <int N>
+__device__ __forceinline__ void face_basis(const Tab& tb, int d, int s, int qt1, int qt2, int tq, double& v,
+                                           double g[3]) {
+    const int ii[3] = {tq / (N * N), (tq / N) % N, tq % N};
+    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int an = (d == 0) ? ii[0] : ((d == 1) ? ii[1] : ii[2]);
+    const int a1 = (t1 == 0) ? ii[0] : ii[1];
+    const int a2 = (t2 == 1) ? ii[1] : ii[2];
+    const double ln = tb.Le[s][an], dn = tb.Lde[s][an];
+    const double v1 = tb.V[qt1][a1], d1 = tb.Vd[qt1][a1];
+    const double v2 = tb.V[qt2][a2], d2 = tb.Vd[qt2][a2];
+    v = ln * v1 * v2;
+    double gd = dn * v1 * v2, g1 = ln * d1 * v2, g2 = ln * v1 * d2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = (k == d) ? gd : ((k == t1) ? g1 : g2);
+}
+
+// Coarse face-coupling blocks dR_e[S]/dW_nb[S] of face f (S = modes of
+// degree <= PC, all equations): the dependence of the face-f integrand of
+// element e on the neighbour's trace, linearised with dual numbers and tested
+// with the coarse modes of e.  One workgroup per (element, face).  A face
+// whose neighbour is the element itself (one-element periodic axis) belongs to
+// the diagonal block: its block is zero here.
+template <int P, int PC, bool NS, bool CURVED>
+__global__ void __launch_bounds__(256) offdiag_kernel(MeshDev m, Gas gas, const double* __restrict__ W,
+                                                      double* __restrict__ out) {
+    constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NB = 5 * NQ;
+    constexpr int NC = PC + 1, NVC = NC * NC * NC, NBC = 5 * NVC;
+    constexpr int CB = 256 / NF;
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int e = blockIdx.x, f = blockIdx.y;
+    const int d = f >> 1, s = f & 1;
+    const int nb = nbr_of(m, e, f);
+    const int t = threadIdx.x;
+    double* ob = out + ((size_t)e * 6 + f) * NBC * NBC;
+    if (nb == e) {
+        for (int i = t; i < NBC * NBC; i += 256) ob[i] = 0.0;
+        return;
+    }
+    __shared__ double sW[2][NB];
+    __shared__ double sPr[NF][40];
+    __shared__ double sGe[NF][26];
+    __shared__ double sOut[CB * NF][20];
+    __shared__ short sInv[NVC];
+    for (int idx = t; idx < NB; idx += 256) {
+        const int a = idx / NQ, q = idx % NQ;
+        sW[0][a * NQ + q] = W[(size_t)e * NB + a * NQ + perm[q]];
+        sW[1][a * NQ + q] = W[(size_t)nb * NB + a * NQ + perm[q]];
+    }
+    for (int q = t; q < NQ; q += 256) {
+        const int h = perm[q];
+        if (h < NVC) sInv[h] = (short)q;
+    }
+    __syncthreads();
+    if (t < NF) {
+        const int qt1 = t / N, qt2 = t % N;
+        for (int side = 0; side < 2; ++side) {
+            const int se = side == 0 ? s : 1 - s;
+            for (int a = 0; a < 5; ++a) {
+                double v = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+                for (int q = 0; q < NQ; ++q) {
+                    double bv, bg[3];
+                    face_basis<N>(tb, d, se, qt1, qt2, q, bv, bg);
+                    const double w = sW[side][a * NQ + q];
+                    v = fma(bv, w, v);
+                    g0 = fma(bg[0], w, g0);
+                    g1 = fma(bg[1], w, g1);
+                    g2 = fma(bg[2], w, g2);
+                }
+                sPr[t][side * 20 + a] = v;
+                sPr[t][side * 20 + 5 + a * 3 + 0] = g0;
+                sPr[t][side * 20 + 5 + a * 3 + 1] = g1;
+                sPr[t][side * 20 + 5 + a * 3 + 2] = g2;
+            }
+        }
+        double nrm[3], JF, Jip[3][3], Jim[3][3], lp, lm;
+        face_geometry<P, CURVED>(tb, m, e, f, qt1, qt2, nrm, JF, Jip, Jim, lp, lm);
+        for (int k = 0; k < 3; ++k) sGe[t][k] = nrm[k];
+        for (int k = 0; k < 9; ++k) {
+            sGe[t][4 + k] = Jip[k / 3][k % 3];
+            sGe[t][13 + k] = Jim[k / 3][k % 3];
+        }
+        sGe[t][3] = JF;
+        sGe[t][22] = lp;
+        sGe[t][23] = lm;
+        sGe[t][24] = tb.w[qt1] * tb.w[qt2] * JF;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < NBC; c0 += CB) {
+        if (t < CB * NF) {
+            const int col = c0 + t / NF, fq = t % NF;
+            if (col < NBC) {
+                const int beta = col / NVC, jm = col % NVC;
+                const int qt1 = fq / N, qt2 = fq % N;
+                double bv, bg[3];
+                face_basis<N>(tb, d, 1 - s, qt1, qt2, sInv[jm], bv, bg);
+                Dual up[5], gxp[5][3], um[5], gxm[5][3];
+                for (int a = 0; a < 5; ++a) {
+                    up[a] = Dual(sPr[fq][a], 0.0);
+                    um[a] = Dual(sPr[fq][20 + a], a == beta ? bv : 0.0);
+                    for (int k = 0; k < 3; ++k) {
+                        gxp[a][k] = Dual(sPr[fq][5 + a * 3 + k], 0.0);
+                        gxm[a][k] = Dual(sPr[fq][25 + a * 3 + k], a == beta ? bg[k] : 0.0);
+                    }
+                }
+                double nrm[3], Jip[3][3], Jim[3][3];
+                for (int k = 0; k < 3; ++k) nrm[k] = sGe[fq][k];
+                for (int k = 0; k < 9; ++k) {
+                    Jip[k / 3][k % 3] = sGe[fq][4 + k];
+                    Jim[k / 3][k % 3] = sGe[fq][13 + k];
+                }
+                Dual fo[20];
+                face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, sGe[fq][22], sGe[fq][23], sGe[fq][24], gas,
+                                         fo);
+                for (int k = 0; k < 20; ++k) sOut[t][k] = fo[k].d;
+            }
+        }
+        __syncthreads();
+        for (int idx = t; idx < CB * NBC; idx += 256) {
+            const int cc = idx / NBC, row = idx % NBC;
+            const int col = c0 + cc;
+            if (col >= NBC) continue;
+            const int alpha = row / NVC, im = row % NVC;
+            const int tq = sInv[im];
+            double acc = 0.0;
+            for (int fq = 0; fq < NF; ++fq) {
+                double bv, bg[3];
+                face_basis<N>(tb, d, s, fq / N, fq % N, tq, bv, bg);
+                const double* so = sOut[cc * NF + fq];
+                acc = fma(bv, so[alpha], acc);
+                acc = fma(bg[0], so[5 + alpha * 3 + 0], acc);
+                acc = fma(bg[1], so[5 + alpha * 3 + 1], acc);
+                acc = fma(bg[2], so[5 + alpha * 3 + 2], acc);
+            }
+            ob[(size_t)col * NBC + row] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+namespace {
+template <int P, int PC>
+hipError_t launch_offdiag_pc(const DGArgs& a, const double* W, double* out, hipStream_t s) {
+    dim3 grid(a.m.ne, 6), block(256);
+    const bool curved = a.m.vtx != nullptr;
+    if (a.ns) {
+        if (curved) hipLaunchKernelGGL((offdiag_kernel<P, PC, true, true>), grid, block, 0, s, a.m, a.g, W, out);
+        else hipLaunchKernelGGL((offdiag_kernel<P, PC, true, false>), grid, block, 0, s, a.m, a.g, W, out);
+    } else {
+        if (curved) hipLaunchKernelGGL((offdiag_kernel<P, PC, false, true>), grid, block, 0, s, a.m, a.g, W, out);
+        else hipLaunchKernelGGL((offdiag_kernel<P, PC, false, false>), grid, block, 0, s, a.m, a.g, W, out);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_offdiag_blocks(const DGArgs& a, const double* W, int pc, double* out, hipStream_t s) {
+    switch (a.p * 10 + pc) {
+        case 21: return launch_offdiag_pc<2, 1>(a, W, out, s);
+        case 31: return launch_offdiag_pc<3, 1>(a, W, out, s);
+        case 32: return launch_offdiag_pc<3, 2>(a, W, out, s);
+        case 41: return launch_offdiag_pc<4, 1>(a, W, out, s);
+        case 42: return launch_offdiag_pc<4, 2>(a, W, out, s);
+        case 43: return launch_offdiag_pc<4, 3>(a, W, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// y_e = D_e x_e + sum_f O_{e,f} x_nb(e,f) on a coarse level: 7 blocks per
+// element row (column-major, storage SF: double, float or bf16 bits),
+// accumulation in AT (double for FP64/FP32 storage, float for BF16).
+__device__ __forceinline__ float bf16_to_f(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
+template <class SF>
+__device__ __forceinline__ double ld_coef(const SF* p, size_t i) { return (double)p[i]; }
+template <>
+__device__ __forceinline__ double ld_coef<unsigned short>(const unsigned short* p, size_t i) { return bf16_to_f(p[i]); }
+
+template <class SF, class AT>
+__global__ void __launch_bounds__(64) bsr7_kernel(MeshDev m, int nbc, const SF* __restrict__ diag,
+                                                  const SF* __restrict__ off, const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+    extern __shared__ double xs[];       // 7 * nbc
+    const int e = blockIdx.x, t = threadIdx.x;
+    for (int i = t; i < nbc; i += 64) xs[i] = x[(size_t)e * nbc + i];
+    for (int f = 0; f < 6; ++f) {
+        const int nb = nbr_of(m, e, f);
+        for (int i = t; i < nbc; i += 64) xs[(1 + f) * nbc + i] = x[(size_t)nb * nbc + i];
+    }
+    __syncthreads();
+    const SF* db = diag + (size_t)e * nbc * nbc;
+    const SF* obk = off + (size_t)e * 6 * nbc * nbc;
+    for (int r = t; r < nbc; r += 64) {
+        AT acc = 0;
+        for (int c = 0; c < nbc; ++c) acc += (AT)ld_coef(db, (size_t)c * nbc + r) * (AT)xs[c];
+        for (int f = 0; f < 6; ++f) {
+            const SF* ofb = obk + (size_t)f * nbc * nbc;
+            const double* xf = xs + (1 + f) * nbc;
+            for (int c = 0; c < nbc; ++c) acc += (AT)ld_coef(ofb, (size_t)c * nbc + r) * (AT)xf[c];
+        }
+        y[(size_t)e * nbc + r] = (double)acc;
+    }
+}
+
+template <class SF>
+hipError_t launch_bsr7(const DGArgs& a, const SF* diag, const SF* off, const double* x, double* y, int nbc,
+                       hipStream_t s) {
+    using AT = typename std::conditional<std::is_same<SF, unsigned short>::value, float, double>::type;
+    hipLaunchKernelGGL((bsr7_kernel<SF, AT>), dim3(a.m.ne), dim3(64), 7 * nbc * sizeof(double), s, a.m, nbc, diag, off,
+                       x, y);
+    return hipGetLastError();
+}
+template hipError_t launch_bsr7<double>(const DGArgs&, const double*, const double*, const double*, double*, int,
+                                        hipStream_t);
+template hipError_t launch_bsr7<float>(const DGArgs&, const float*, const float*, const double*, double*, int,
+                                       hipStream_t);
+template hipError_t launch_bsr7<unsigned short>(const DGArgs&, const unsigned short*, const unsigned short*,
+                                                const double*, double*, int, hipStream_t);
 
 }  // namespace dg

@@ -115,5 +115,6 @@ template <class TF>
 hipError_t launch_bsr7(const DGArgs& a, const TF* diag, const TF* off, const double* x, double* y, int nbc,
                        hipStream_t s);
 hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s);
+hipError_t launch_convert_fp64_to_bf16(const double* x, unsigned short* y, size_t n, hipStream_t s);
 
 }  // namespace dg

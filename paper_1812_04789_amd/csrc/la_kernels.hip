@@ -206,6 +206,20 @@ __global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restric
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (float)x[i];
 }
+// FP64 -> BF16 bits: round to FP32 (nearest even), then to BF16 (nearest even).
+__global__ void f64_to_bf16_kernel(const double* __restrict__ x, unsigned short* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned int b = __float_as_uint((float)x[i]);
+        const unsigned int r = b + 0x7FFFu + ((b >> 16) & 1u);
+        y[i] = (unsigned short)(r >> 16);
+    }
+}
+hipError_t launch_convert_fp64_to_bf16(const double* x, unsigned short* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(f64_to_bf16_kernel, grid_for(n), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(f64_to_f32_kernel, grid_for(n), dim3(256), 0, s, x, y, n);
     return hipGetLastError();

@@ -135,3 +135,79 @@ def test_bdf2_step_pmg_matches_oracle(fp32, tgv_oracle):
     print("TGV p2: newton", st.newton, "its", st.linear_iters, "rel", st.max_rel_res_true, flush=True)
     assert st.max_rel_res_true <= 1e-8
     assert _rel(W1.cpu().numpy().reshape(Wo.shape), W1o) < 1e-10
+
+
+def test_vcycle_graph_replays_match_eager():
+    """pmg_apply replays a captured HIP graph; every replay, with other eager
+    work and synchronisations in between, equals the eager V-cycle bitwise
+    (all kernels, reductions included, are deterministic)."""
+    ctx, _ = _case((2, 3, 2), 2, 0.02, True)
+    W = _dev(inputs.random_state(ctx.ne, 2, seed=51))
+    r1 = _dev(inputs.random_vector(ctx.ne, 2, seed=52))
+    r2 = _dev(inputs.random_vector(ctx.ne, 2, seed=53))
+    ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12))
+    ctx.use_graphs(False)
+    z1 = ctx.pmg_apply(r1).clone()
+    z2 = ctx.pmg_apply(r2).clone()
+    ctx.use_graphs(True)
+    for i in range(4):
+        g1 = ctx.pmg_apply(r1)
+        ctx.residual(W)                          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(g1, z1), i
+        g2 = ctx.pmg_apply(r2)
+        torch.cuda.synchronize()
+        assert torch.equal(g2, z2), i
+
+
+@pytest.mark.parametrize("p,pc,curved", [(2, 1, True), (3, 1, False), (3, 2, True)])
+def test_coarse_face_blocks_are_jacobian_blocks(p, pc, curved):
+    """Face-coupling blocks of the inherited coarse operator equal the exact
+    Jacobian columns: perturbing a coarse mode of the neighbour across face f
+    changes R_e only through face f (3^3 mesh: each neighbour is across one face)."""
+    n = (3, 3, 3)
+    ctx, D = _case(n, p, 0.02, curved)
+    W = inputs.random_state(ctx.ne, p, seed=61)
+    off = ctx.assemble_coarse(_dev(W), pc).cpu().numpy()      # [e][f][col][row]
+    nvc = (pc + 1) ** 3
+    rows = olin.sub_block_index(D.nv, nvc)
+    rng = np.random.default_rng(p * 10 + pc)
+    e = 13
+    for f in range(6):
+        nb = D.mesh.nbr[e, f]
+        for col in rng.choice(5 * nvc, 3, replace=False):
+            beta, jm = divmod(int(col), nvc)
+            v = np.zeros_like(W)
+            v[nb, beta, jm] = 1.0
+            ref = olin.jvp_exact(D, W, v, 0.0)[e].reshape(-1)[rows]
+            got = off[e, f, col]
+            assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (f, col)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_pmg_assembled_coarse_vcycle(prec):
+    """V-cycle with assembled inherited coarse operators against the oracle's
+    V-cycle with the exact P^T K_0 P (FP64: 1e-5, FD rounding on level 0);
+    BF16 coarse storage (RNE, FP32 accumulation) stays within 1e-2."""
+    ctx, D = _case((2, 2, 2), 2, 0.02, False)
+    W = inputs.random_state(ctx.ne, 2, seed=63)
+    r = inputs.random_vector(ctx.ne, 2, seed=64)
+    a = 20.0
+    pc = binding.DG_BF16 if prec == "bf16" else binding.DG_FP64
+    ctx.pmg_setup(_dev(W), a, binding.pmg_opts([2, 1], coarsest_iters=10, prec_coarse=pc, coarse_matrix_free=0))
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.PMG(D, W, a, [2, 1], coarse_iters=10, coarse_op="exact").apply(r)
+    assert _rel(z, zo) < (1e-2 if prec == "bf16" else 1e-5)
+
+
+def test_bdf2_step_mixed_bf16_matches_oracle(tgv_oracle):
+    """Mixed precision (FP32 fine factors, BF16 assembled coarse level): the
+    converged W^{n+1} still matches the FP64 oracle."""
+    D, Wo, W1o = tgv_oracle
+    ctx, _ = _case((3, 3, 3), 2, 1.0 / 1600, True, amp=0.05)
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.1)))
+    popts = binding.pmg_opts([2, 1], prec_fine=binding.DG_FP32, prec_coarse=binding.DG_BF16, coarse_matrix_free=0)
+    W1, st = ctx.bdf2_step(Wg, None, 0.05, popts, binding.fgmres_opts(restart=40, rtol=1e-8))
+    print("TGV p2 mixed bf16: newton", st.newton, "its", st.linear_iters, flush=True)
+    assert st.max_rel_res_true <= 1e-8
+    assert _rel(W1.cpu().numpy().reshape(Wo.shape), W1o) < 1e-10
