@@ -86,6 +86,9 @@ struct Level {
     DBuf<float> f32;      // factors (FP32)
     DBuf<int> piv, pos;
     bool use32 = false;
+    bool inv = false;          // explicit inverse (nb <= INV_MAX_N) applied by GEMV
+    DBuf<double> inv64;
+    DBuf<float> inv32;
     DBuf<double> x, b, r, t, z;
     // assembled inherited operator: diagonal + 6 face blocks per element
     bool assembled = false;
@@ -93,7 +96,7 @@ struct Level {
     DBuf<double> od64, oo64;
     DBuf<float> od32, oo32;
     DBuf<unsigned short> od16, oo16;
-    void release() { od64.release(); oo64.release(); od32.release(); oo32.release(); od16.release(); oo16.release();
+    void release() { inv64.release(); inv32.release(); od64.release(); oo64.release(); od32.release(); oo32.release(); od16.release(); oo16.release();
                      f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
 };
 
@@ -120,7 +123,7 @@ struct dg_ctx {
     bool pmg_ready = false;
     pmg_opts popt{};
     double shift = 0.0;
-    DBuf<double> W0, RW0, blk, otmp, dtmp;
+    DBuf<double> W0, RW0, blk, otmp, dtmp, nbrtr;
     std::vector<Level> lv;
     Krylov kc;                              // coarsest-level GMRES
     Krylov kf;                              // outer FGMRES
@@ -215,6 +218,9 @@ void bj_apply(dg_ctx* ctx, int l, const double* r, double* z) {
     Level& L = ctx->lv[l];
     const double nbl = L.nb, sf = L.use32 ? 4.0 : 8.0;
     timed(ctx, DG_K_LU_SOLVE, ctx->ne * (sf * nbl * nbl + 20.0 * nbl), ctx->ne * 2.0 * nbl * nbl, [&] {
+        if (L.inv)
+            return L.use32 ? launch_inv_gemv<float>(L.inv32.p, r, z, ctx->ne, L.nb, ctx->s)
+                           : launch_inv_gemv<double>(L.inv64.p, r, z, ctx->ne, L.nb, ctx->s);
         return L.use32 ? launch_lu_solve_blocked<float>(L.f32.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s)
                        : launch_lu_solve_blocked<double>(L.f64.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s);
     });
@@ -393,7 +399,8 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     dot(ctx, ctx->W0.p, ctx->W0.p, N, sc(ctx, S_PMG_NW2));
     const int nb = ctx->nb;
     ctx->blk.ensure((size_t)ctx->ne * nb * nb);
-    timed(ctx, DG_K_DIAG_BLOCKS, 8.0 * ctx->ne * (double)nb * nb + 8.0 * (double)ctx->N, 0.0, [&] { return launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->s); });
+    ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
+    timed(ctx, DG_K_DIAG_BLOCKS, 8.0 * ctx->ne * (double)nb * nb + 8.0 * (double)ctx->N, 0.0, [&] { return launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->nbrtr.p, ctx->s); });
     for (size_t l = o->n_levels; l < ctx->lv.size(); ++l) ctx->lv[l].release();
     ctx->lv.resize(o->n_levels);
     for (int l = 0; l < o->n_levels; ++l) {
@@ -460,6 +467,30 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     if (!ctx->lv[0].use32) {
         std::swap(ctx->lv[0].f64.p, ctx->blk.p);
         std::swap(ctx->lv[0].f64.n, ctx->blk.n);
+    }
+    // explicit inverses for the smoother apply: FP32 blocks up to INV_MAX_N
+    // and every block up to 135.  The inverse costs about as much as the PLU
+    // itself; for large FP64 blocks the blocked triangular solves are cheaper
+    // over the ~100 applies of one time step.
+    for (int l = 0; l < o->n_levels; ++l) {
+        Level& L = ctx->lv[l];
+        L.inv = L.nb <= (L.use32 ? INV_MAX_N : 135);
+        if (!L.inv) continue;
+        const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
+        const double fl = ctx->ne * 2.0 * (double)L.nb * L.nb * L.nb;
+        if (L.use32) {
+            ctx->blk.ensure(sz);          // FP64 workspace (the FP64 blocks are no longer needed)
+            L.inv32.ensure(sz);
+            timed(ctx, DG_K_LU, 4.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
+                return launch_lu_inverse<float>(L.f32.p, L.pos.p, ctx->blk.p, L.inv32.p, ctx->ne, L.nb, ctx->s);
+            });
+        } else {
+            L.inv64.ensure(sz);
+            timed(ctx, DG_K_LU, 8.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
+                return launch_lu_inverse<double>(L.f64.p, L.pos.p, L.inv64.p, (double*)nullptr, ctx->ne, L.nb,
+                                                 ctx->s);
+            });
+        }
     }
     if (o->n_levels > 1) {
         const Level& Lc = ctx->lv.back();
@@ -741,7 +772,7 @@ dg_status dg_destroy(dg_ctx* ctx) {
     ctx->gout.release();
     ctx->vtx.release(); ctx->partial.release(); ctx->scal.release(); ctx->flag.release();
     ctx->tmp1.release(); ctx->tmp2.release(); ctx->tmp3.release();
-    ctx->W0.release(); ctx->RW0.release(); ctx->blk.release(); ctx->otmp.release(); ctx->dtmp.release();
+    ctx->W0.release(); ctx->RW0.release(); ctx->blk.release(); ctx->otmp.release(); ctx->dtmp.release(); ctx->nbrtr.release();
     for (auto& L : ctx->lv) L.release();
     ctx->kc.release(); ctx->kf.release();
     ctx->RW.release(); ctx->Ru.release(); ctx->xN.release();
@@ -817,7 +848,8 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
     return guarded(ctx, [&] {
         need(ctx, W, "W");
         need(ctx, blocks, "blocks");
-        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->s));
+        ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
+        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->nbrtr.p, ctx->s));
     });
 }
 

@@ -794,9 +794,6 @@ hipError_t launch_jvp_exact(const DGArgs& a, const double* W, const double* v, d
                             hipStream_t s) {
     return dispatch_dg<M_TANGENT>(a, W, v, nullptr, nullptr, shift, y, s);
 }
-hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, hipStream_t s) {
-    return dispatch_dg<M_DIAGCOL>(a, W, nullptr, nullptr, nullptr, shift, blocks, s);
-}
 hipError_t launch_mass(const DGArgs& a, const double* v, double* y, double scale, int accumulate, hipStream_t s) {
     switch (a.p) {
         case 1: return launch_mass_p<1>(a, v, y, scale, accumulate, s);
@@ -1125,5 +1122,331 @@ template hipError_t launch_bsr7<float>(const DGArgs&, const float*, const float*
                                        hipStream_t);
 template hipError_t launch_bsr7<unsigned short>(const DGArgs&, const unsigned short*, const unsigned short*,
                                                 const double*, double*, int, hipStream_t);
+
+// ---- element diagonal blocks (Sec. 6.3) ------------------------------------------------------
+// Column j = (beta, mode) of K_e = a M_e + dR_e/dW_e is the forward-mode
+// derivative of the element residual when only W_e[beta][mode] moves.  The
+// neighbours' traces do not move, so they are evaluated once per element
+// (nbr_trace_kernel) and read as plain values; the own tangent is the basis
+// function itself (value and reference gradient from the 1D tables); only
+// tangent parts are carried through the face integrands and the test.
+template <int P>
+__global__ void __launch_bounds__(256) nbr_trace_kernel(MeshDev m, const double* __restrict__ W,
+                                                        double* __restrict__ out) {
+    constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NB = 5 * NQ;
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int e = blockIdx.x, t = threadIdx.x;
+    if (t >= 6 * NF) return;
+    const int f = t / NF, fq = t % NF;
+    const int d = f >> 1, s = f & 1;
+    const int nb = nbr_of(m, e, f);
+    const double* wn = W + (size_t)nb * NB;
+    double acc[20];
+    for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        double bv, bg[3];
+        face_basis<N>(tb, d, 1 - s, fq / N, fq % N, q, bv, bg);
+        const int pm = perm[q];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const double w = wn[a * NQ + pm];
+            acc[a] = fma(bv, w, acc[a]);
+            acc[5 + a * 3 + 0] = fma(bg[0], w, acc[5 + a * 3 + 0]);
+            acc[5 + a * 3 + 1] = fma(bg[1], w, acc[5 + a * 3 + 1]);
+            acc[5 + a * 3 + 2] = fma(bg[2], w, acc[5 + a * 3 + 2]);
+        }
+    }
+    double* o = out + (((size_t)e * 6 + f) * NF + fq) * 20;
+    for (int k = 0; k < 20; ++k) o[k] = acc[k];
+}
+
+template <int P>
+struct SzD {
+    static constexpr int N = P + 1, NQ = N * N * N, NF = N * N;
+    static constexpr int OFF_U = 20 * NQ;                 // [0, 20NQ): interpolation buffers, later test A/B
+    static constexpr int OFF_G = OFF_U + 5 * NQ;          // Gauss values (5NQ), reference gradients (15NQ)
+    static constexpr int OFF_F = OFF_G + 15 * NQ;         // face integrand tangents (120 NF)
+    static constexpr int OFF_H = OFF_F + 120 * NF;        // test-back sweeps (15 NQ)
+    static constexpr int TOT = OFF_H + 15 * NQ;
+};
+template <int P> struct LaunchD { static constexpr int EPB = (P == 1) ? 8 : ((P == 2) ? 2 : 1); };
+
+template <int P, bool NS, bool CURVED>
+__global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
+    diag_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ nbrtr, double shift,
+                double* __restrict__ out) {
+    using S_ = SzD<P>;
+    constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = 5 * NQ;
+    constexpr int EPB = LaunchD<P>::EPB;
+    __shared__ double smem[EPB * S_::TOT];
+    __shared__ double sdet[EPB][NQ];
+    __shared__ double svtx[EPB][24];
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const int e = blockIdx.x * EPB + es;
+    const bool active = e < m.ne;
+    const int col = blockIdx.y;
+    const int beta = col / NQ, hj = col % NQ;
+    double* S = smem + es * S_::TOT;
+    const int ii[3] = {q / NF, (q / N) % N, q % N};
+    // tensor mode of column j (hierarchical index hj)
+    __shared__ int stj;
+    if (threadIdx.x < NQ && perm[threadIdx.x] == hj) stj = threadIdx.x;
+    if (active) {
+        const size_t base = (size_t)e * NB;
+        const int pm = perm[q];
+        for (int a = 0; a < 5; ++a) S[a * NQ + q] = W[base + a * NQ + pm];
+        if constexpr (CURVED)
+            for (int k = q; k < 24; k += NQ) svtx[es][k] = m.vtx[(size_t)e * 24 + k];
+    }
+    __syncthreads();
+    const int tj = stj;
+    const int jj[3] = {tj / NF, (tj / N) % N, tj % N};
+    double* X1 = S + 5 * NQ;
+    double* X2 = S + 10 * NQ;
+    double* su = S + S_::OFF_U;
+    double* sg = S + S_::OFF_G;
+    if (active) sweep<N, 5, false>(tb.V, S, X1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X1, X2, 1, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X2, su, 2, ii, q);
+    __syncthreads();
+    double Ad[5][3], Bd[5];
+    double detJ = 1.0, Ji[3][3];
+    const double hx = m.h[0], hy = m.h[1], hz = m.h[2];
+    if (active) {
+        Dual u[5], gx[5][3];
+        // tangent of column j at this Gauss point: phi_j and its reference gradient
+        const double p0 = tb.V[ii[0]][jj[0]], p1 = tb.V[ii[1]][jj[1]], p2 = tb.V[ii[2]][jj[2]];
+        const double phi = p0 * p1 * p2;
+        const double dphi[3] = {tb.Vd[ii[0]][jj[0]] * p1 * p2, p0 * tb.Vd[ii[1]][jj[1]] * p2,
+                                p0 * p1 * tb.Vd[ii[2]][jj[2]]};
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            u[a] = Dual(su[a * NQ + q], a == beta ? phi : 0.0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc = fma(tb.D[ii[k]][j], su[a * NQ + tix_dir<N>(k, j, ii)], acc);
+                gx[a][k] = Dual(acc, a == beta ? dphi[k] : 0.0);
+                sg[(a * 3 + k) * NQ + q] = acc;
+            }
+        }
+        if constexpr (CURVED) {
+            double J[3][3];
+            q1_jac(svtx[es], tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
+            detJ = q1_inv(J, Ji);
+            sdet[es][q] = detJ;
+        } else {
+            detJ = 0.125 * hx * hy * hz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Ji[k][d] = 0.0;
+            Ji[0][0] = 2.0 / hx;
+            Ji[1][1] = 2.0 / hy;
+            Ji[2][2] = 2.0 / hz;
+        }
+        const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]];
+        Dual F[5][3];
+        flux_c(u, gas.gamma - 1.0, F);
+        if constexpr (NS) {
+            Dual g[5][3];
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    g[a][j] = Ji[0][j] * gx[a][0] + Ji[1][j] * gx[a][1] + Ji[2][j] * gx[a][2];
+            flux_v_acc(u, g, gas, 1.0, F);
+        }
+        const double c = -wq * detJ;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Ad[a][k] = c * (Ji[k][0] * F[a][0].d + Ji[k][1] * F[a][1].d + Ji[k][2] * F[a][2].d);
+            Bd[a] = (a == beta) ? shift * wq * detJ * phi : 0.0;
+        }
+    }
+    __syncthreads();
+    double* sF = S + S_::OFF_F;
+    if (active) {
+        for (int fp = q; fp < 6 * NF; fp += NQ) {
+            const int f = fp / NF, fq = fp % NF;
+            const int d = f >> 1, s = f & 1;
+            const int t1 = (d == 0) ? 1 : 0;
+            const int qt1 = fq / N, qt2 = fq % N;
+            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            const int tl = qt1 * st1 + qt2 * st2;
+            const int nb = nbr_of(m, e, f);
+            Dual up[5], gxp[5][3], um[5], gxm[5][3];
+            double bvp, bgp[3];
+            face_basis<N>(tb, d, s, qt1, qt2, tj, bvp, bgp);
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                double v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int tt = tl + k * sd;
+                    const double l = tb.lag[s][k];
+                    v0 = fma(l, su[a * NQ + tt], v0);
+                    g0 = fma(l, sg[(a * 3 + 0) * NQ + tt], g0);
+                    g1 = fma(l, sg[(a * 3 + 1) * NQ + tt], g1);
+                    g2 = fma(l, sg[(a * 3 + 2) * NQ + tt], g2);
+                }
+                const bool on = a == beta;
+                up[a] = Dual(v0, on ? bvp : 0.0);
+                gxp[a][0] = Dual(g0, on ? bgp[0] : 0.0);
+                gxp[a][1] = Dual(g1, on ? bgp[1] : 0.0);
+                gxp[a][2] = Dual(g2, on ? bgp[2] : 0.0);
+            }
+            if (nb == e) {
+                // one-element periodic axis: the neighbour trace is this element's
+                // trace on the opposite face, and it moves with W_e
+                double bvm, bgm[3];
+                face_basis<N>(tb, d, 1 - s, qt1, qt2, tj, bvm, bgm);
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    double v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        const int tt = tl + k * sd;
+                        const double l = tb.lag[1 - s][k];
+                        v0 = fma(l, su[a * NQ + tt], v0);
+                        g0 = fma(l, sg[(a * 3 + 0) * NQ + tt], g0);
+                        g1 = fma(l, sg[(a * 3 + 1) * NQ + tt], g1);
+                        g2 = fma(l, sg[(a * 3 + 2) * NQ + tt], g2);
+                    }
+                    const bool on = a == beta;
+                    um[a] = Dual(v0, on ? bvm : 0.0);
+                    gxm[a][0] = Dual(g0, on ? bgm[0] : 0.0);
+                    gxm[a][1] = Dual(g1, on ? bgm[1] : 0.0);
+                    gxm[a][2] = Dual(g2, on ? bgm[2] : 0.0);
+                }
+            } else {
+                const double* nt = nbrtr + (((size_t)e * 6 + f) * NF + fq) * 20;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    um[a] = Dual(nt[a], 0.0);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gxm[a][k] = Dual(nt[5 + a * 3 + k], 0.0);
+                }
+            }
+            double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
+            if constexpr (CURVED) {
+                face_geometry<P, true>(tb, m, e, f, qt1, qt2, nrm, JF, Jip, Jim, lam_p, lam_m);
+            } else {
+                face_geometry<P, false>(tb, m, e, f, qt1, qt2, nrm, JF, Jip, Jim, lam_p, lam_m);
+            }
+            (void)t1;
+            Dual fo[20];
+            face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
+                                     fo);
+            double* so = sF + (f * NF + fq) * 20;
+#pragma unroll
+            for (int k = 0; k < 20; ++k) so[k] = fo[k].d;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            const double l = tb.lag[s][ii[d]];
+            const double* fo = sF + (f * NF + ii[t1] * N + ii[t2]) * 20;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                Bd[a] = fma(l, fo[a], Bd[a]);
+                if constexpr (NS) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) Ad[a][k] = fma(l, fo[5 + a * 3 + k], Ad[a][k]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* sA = S;
+    double* sB = S + 15 * NQ;
+    double* H = S + S_::OFF_H;
+    double* Y1 = S + S_::OFF_U;         // Gauss values no longer needed
+    double* Y2 = S + S_::OFF_G;
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sA[(a * 3 + k) * NQ + q] = Ad[a][k];
+            sB[a * NQ + q] = Bd[a];
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            double acc = sB[a * NQ + q];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                    acc = fma(tb.D[j][ii[k]], sA[(a * 3 + k) * NQ + tix_dir<N>(k, j, ii)], acc);
+            H[a * NQ + q] = acc;
+        }
+    }
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, H, Y1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, true>(tb.V, Y1, Y2, 1, ii, q);
+    __syncthreads();
+    if (active) {
+        const int pm = perm[q];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], Y2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+            out[((size_t)e * NB + col) * NB + a * NQ + pm] = acc;
+        }
+    }
+}
+
+namespace {
+template <int P>
+hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+                         hipStream_t s) {
+    constexpr int NQ = (P + 1) * (P + 1) * (P + 1);
+    hipLaunchKernelGGL(nbr_trace_kernel<P>, dim3(a.m.ne), dim3(256), 0, s, a.m, W, nbrtr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr int EPB = LaunchD<P>::EPB;
+    dim3 grid((a.m.ne + EPB - 1) / EPB, 5 * NQ), block(EPB * NQ);
+    const bool curved = a.m.vtx != nullptr;
+    if (a.ns) {
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, true, true>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        else hipLaunchKernelGGL((diag_kernel<P, true, false>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+    } else {
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, false, true>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        else hipLaunchKernelGGL((diag_kernel<P, false, false>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+size_t nbr_trace_size(int p, int ne) { return (size_t)ne * 6 * (p + 1) * (p + 1) * 20; }
+
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+                              hipStream_t s) {
+    switch (a.p) {
+        case 1: return launch_diag_p<1>(a, W, shift, blocks, nbrtr, s);
+        case 2: return launch_diag_p<2>(a, W, shift, blocks, nbrtr, s);
+        case 3: return launch_diag_p<3>(a, W, shift, blocks, nbrtr, s);
+        case 4: return launch_diag_p<4>(a, W, shift, blocks, nbrtr, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace dg

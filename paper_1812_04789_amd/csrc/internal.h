@@ -59,7 +59,10 @@ hipError_t launch_jvp_fd(const DGArgs& a, const double* W, const double* RW, con
                          double shift, double* y, hipStream_t s);
 hipError_t launch_jvp_exact(const DGArgs& a, const double* W, const double* v, double shift, double* y,
                             hipStream_t s);
-hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, hipStream_t s);
+// nbrtr: scratch of nbr_trace_size(p, ne) doubles (neighbour traces at the face points)
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+                              hipStream_t s);
+size_t nbr_trace_size(int p, int ne);
 // Coarse face-coupling blocks: for every element e, face f, the (nbc x nbc)
 // block dR_e[S]/dW_nb(f)[S] over the coarse-mode set S of degree pc (rows and
 // columns equation-major over S), column-major.  out [ne][6][nbc][nbc].
@@ -107,6 +110,13 @@ hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStre
 template <class TF>
 hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
                                    hipStream_t s);
+// Explicit inverse of PLU-factored blocks (n <= 320): FP64 workspace Xw
+// [nblk][n][n]; Xout (TF, may be null when TF is double and Xw is used directly).
+template <class TF>
+hipError_t launch_lu_inverse(const TF* LU, const int* pos, double* Xw, TF* Xout, int nblk, int n, hipStream_t s);
+template <class TF>
+hipError_t launch_inv_gemv(const TF* X, const double* r, double* z, int nblk, int n, hipStream_t s);
+constexpr int INV_MAX_N = 320;
 // Extract coarse principal sub-blocks (FP64 column-major fine blocks) and round to TF.
 template <class TF>
 hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);

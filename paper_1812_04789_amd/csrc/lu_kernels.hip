@@ -418,4 +418,226 @@ template hipError_t launch_lu_solve_blocked<double>(const double*, const int*, c
 template hipError_t launch_lu_solve_blocked<float>(const float*, const int*, const double*, double*, int, int,
                                                    hipStream_t);
 
+// ---- explicit block inverse for the smoother apply --------------------------------------------
+// X = A^-1 from the PLU factors: X starts as P I (X[c][i] = 1 iff pos[i] = c)
+// and is overwritten by L^-1 then U^-1 in INV_TB-row panels over all n
+// right-hand sides (panel of the factor and panel rows of X staged in LDS,
+// 4x4 register tiles for the updates).  X is column-major FP64 (workspace),
+// rounded to the storage type TF at the end.  Blocks up to n = 320.
+constexpr int INV_TB = 24;
+
+size_t lu_inverse_lds(int n) { return (size_t)2 * INV_TB * n * sizeof(double); }
+
+template <class TF>
+__global__ void __launch_bounds__(LU_THREADS) lu_inverse_kernel(const TF* __restrict__ LU, const int* __restrict__ pos,
+                                                                double* __restrict__ Xw, TF* __restrict__ Xout, int n) {
+    extern __shared__ double lds[];
+    double* Fp = lds;                          // factor panel: Fp[j*n + i]
+    double* Xp = lds + (size_t)INV_TB * n;     // X panel rows: Xp[j*n + c]
+    const TF* a = LU + (size_t)blockIdx.x * n * n;
+    const int* po = pos + (size_t)blockIdx.x * n;
+    double* X = Xw + (size_t)blockIdx.x * n * n;
+    const int t = threadIdx.x;
+    for (size_t idx = t; idx < (size_t)n * n; idx += LU_THREADS) X[idx] = 0.0;
+    __syncthreads();
+    for (int i = t; i < n; i += LU_THREADS) X[(size_t)po[i] * n + i] = 1.0;
+    __syncthreads();
+    // forward: L (unit lower)
+    for (int k0 = 0; k0 < n; k0 += INV_TB) {
+        const int kb = min(INV_TB, n - k0), m = n - k0;
+        for (int idx = t; idx < m * kb; idx += LU_THREADS) {
+            const int j = idx / m, i = idx % m;
+            Fp[j * n + i] = (double)a[(size_t)(k0 + j) * n + k0 + i];
+        }
+        __syncthreads();
+        for (int c = t; c < n; c += LU_THREADS) {
+            double x[INV_TB];
+#pragma unroll
+            for (int j = 0; j < INV_TB; ++j) x[j] = (j < kb) ? X[(size_t)c * n + k0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < INV_TB; ++j)
+#pragma unroll
+                for (int i = j + 1; i < INV_TB; ++i)
+                    if (i < kb) x[i] -= Fp[j * n + i] * x[j];
+#pragma unroll
+            for (int j = 0; j < INV_TB; ++j)
+                if (j < kb) {
+                    X[(size_t)c * n + k0 + j] = x[j];
+                    Xp[j * n + c] = x[j];
+                }
+        }
+        __syncthreads();
+        const int m2 = n - k0 - kb;
+        if (m2 > 0) {
+            const int tr = (m2 + 3) / 4, tc = (n + 3) / 4;
+            for (int tile = t; tile < tr * tc; tile += LU_THREADS) {
+                const int r0 = (tile % tr) * 4, c0 = (tile / tr) * 4;
+                double acc[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+                for (int j = 0; j < kb; ++j) {
+                    double lv[4], xv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < m2) ? Fp[j * n + kb + r0 + i] : 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) xv[jj] = (c0 + jj < n) ? Xp[j * n + c0 + jj] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(lv[i], xv[jj], acc[i][jj]);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (c0 + jj >= n) continue;
+                    double* colp = X + (size_t)(c0 + jj) * n + k0 + kb + r0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (r0 + i < m2) colp[i] -= acc[i][jj];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // backward: U (upper, non-unit)
+    const int nb0 = ((n - 1) / INV_TB) * INV_TB;
+    for (int k0 = nb0; k0 >= 0; k0 -= INV_TB) {
+        const int kb = min(INV_TB, n - k0), m = k0 + kb;
+        for (int idx = t; idx < m * kb; idx += LU_THREADS) {
+            const int j = idx / m, i = idx % m;
+            Fp[j * n + i] = (double)a[(size_t)(k0 + j) * n + i];
+        }
+        __syncthreads();
+        for (int c = t; c < n; c += LU_THREADS) {
+            double x[INV_TB];
+#pragma unroll
+            for (int j = 0; j < INV_TB; ++j) x[j] = (j < kb) ? X[(size_t)c * n + k0 + j] : 0.0;
+#pragma unroll
+            for (int j = INV_TB - 1; j >= 0; --j) {
+                if (j < kb) {
+                    x[j] /= Fp[j * n + k0 + j];
+#pragma unroll
+                    for (int i = 0; i < j; ++i) x[i] -= Fp[j * n + k0 + i] * x[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < INV_TB; ++j)
+                if (j < kb) {
+                    X[(size_t)c * n + k0 + j] = x[j];
+                    Xp[j * n + c] = x[j];
+                }
+        }
+        __syncthreads();
+        if (k0 > 0) {
+            const int tr = (k0 + 3) / 4, tc = (n + 3) / 4;
+            for (int tile = t; tile < tr * tc; tile += LU_THREADS) {
+                const int r0 = (tile % tr) * 4, c0 = (tile / tr) * 4;
+                double acc[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+                for (int j = 0; j < kb; ++j) {
+                    double uv[4], xv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) uv[i] = (r0 + i < k0) ? Fp[j * n + r0 + i] : 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) xv[jj] = (c0 + jj < n) ? Xp[j * n + c0 + jj] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(uv[i], xv[jj], acc[i][jj]);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (c0 + jj >= n) continue;
+                    double* colp = X + (size_t)(c0 + jj) * n + r0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (r0 + i < k0) colp[i] -= acc[i][jj];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (Xout) {
+        TF* xo = Xout + (size_t)blockIdx.x * n * n;
+        for (size_t idx = t; idx < (size_t)n * n; idx += LU_THREADS) xo[idx] = (TF)X[idx];
+    }
+}
+
+template <class TF>
+hipError_t launch_lu_inverse(const TF* LU, const int* pos, double* Xw, TF* Xout, int nblk, int n, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    const size_t lds = lu_inverse_lds(n);
+    hipError_t e = hipFuncSetAttribute((const void*)lu_inverse_kernel<TF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lu_inverse_kernel<TF>, dim3(nblk), dim3(LU_THREADS), lds, s, LU, pos, Xw, Xout, n);
+    return hipGetLastError();
+}
+template hipError_t launch_lu_inverse<double>(const double*, const int*, double*, double*, int, int, hipStream_t);
+template hipError_t launch_lu_inverse<float>(const float*, const int*, double*, float*, int, int, hipStream_t);
+
+// z = X r per block with the explicit inverse (column-major, storage TF).
+// Four wavefronts per block, wavefront w takes columns c = w (mod 4) two at a
+// time; lane i accumulates rows i, i+64, ... (every column read is a
+// contiguous run of rows); the four partial sums are added in a fixed order.
+// FP64 accumulation.
+constexpr int GEMV_THREADS = 256;
+constexpr int GEMV_ROWS = 5;     // rows per lane (n <= 320)
+
+template <class TF>
+__global__ void __launch_bounds__(GEMV_THREADS)
+    inv_gemv_kernel(const TF* __restrict__ X, const double* __restrict__ r, double* __restrict__ z, int n) {
+    extern __shared__ double rs[];             // n entries of r, then 4 x n partial sums
+    double* part = rs + n;
+    const TF* xb = X + (size_t)blockIdx.x * n * n;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int i = t; i < n; i += GEMV_THREADS) rs[i] = r[(size_t)blockIdx.x * n + i];
+    __syncthreads();
+    double acc[GEMV_ROWS];
+#pragma unroll
+    for (int k = 0; k < GEMV_ROWS; ++k) acc[k] = 0.0;
+    int c = w;
+    for (; c + 4 < n; c += 8) {
+        const double r0 = rs[c], r1 = rs[c + 4];
+        const TF* c0 = xb + (size_t)c * n;
+        const TF* c1 = xb + (size_t)(c + 4) * n;
+#pragma unroll
+        for (int k = 0; k < GEMV_ROWS; ++k) {
+            const int i = lane + k * 64;
+            if (i < n) acc[k] = fma((double)c1[i], r1, fma((double)c0[i], r0, acc[k]));
+        }
+    }
+    for (; c < n; c += 4) {
+        const double r0 = rs[c];
+        const TF* c0 = xb + (size_t)c * n;
+#pragma unroll
+        for (int k = 0; k < GEMV_ROWS; ++k) {
+            const int i = lane + k * 64;
+            if (i < n) acc[k] = fma((double)c0[i], r0, acc[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < GEMV_ROWS; ++k) {
+        const int i = lane + k * 64;
+        if (i < n) part[w * n + i] = acc[k];
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += GEMV_THREADS)
+        z[(size_t)blockIdx.x * n + i] = ((part[i] + part[n + i]) + part[2 * n + i]) + part[3 * n + i];
+}
+
+template <class TF>
+hipError_t launch_inv_gemv(const TF* X, const double* r, double* z, int nblk, int n, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    if (n > 64 * GEMV_ROWS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(inv_gemv_kernel<TF>, dim3(nblk), dim3(GEMV_THREADS), 5 * n * sizeof(double), s, X, r, z, n);
+    return hipGetLastError();
+}
+template hipError_t launch_inv_gemv<double>(const double*, const double*, double*, int, int, hipStream_t);
+template hipError_t launch_inv_gemv<float>(const float*, const double*, double*, int, int, hipStream_t);
+
 }  // namespace dg

@@ -211,3 +211,17 @@ def test_bdf2_step_mixed_bf16_matches_oracle(tgv_oracle):
     print("TGV p2 mixed bf16: newton", st.newton, "its", st.linear_iters, flush=True)
     assert st.max_rel_res_true <= 1e-8
     assert _rel(W1.cpu().numpy().reshape(Wo.shape), W1o) < 1e-10
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_block_jacobi_parity_high_order(p):
+    """p = 3 applies the explicit block inverse (GEMV), p = 4 the blocked
+    triangular solves; both equal the oracle's PLU solve."""
+    ctx, D = _case((2, 1, 1), p, 0.02, True)
+    W = inputs.random_state(ctx.ne, p, seed=71)
+    r = inputs.random_vector(ctx.ne, p, seed=72)
+    a = 20.0
+    ctx.pmg_setup(_dev(W), a, binding.pmg_opts([p]))
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.BlockJacobi(D, W, a).apply(r)
+    assert _rel(z, zo) < 1e-10
