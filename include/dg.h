@@ -79,7 +79,8 @@ typedef struct {
  *                 must decrease.  n_levels == 1 is the single-grid element
  *                 block-Jacobi preconditioner z = D^-1 r.
  *  nu_pre/nu_post damped block-Jacobi sweeps x += omega D^-1 (b - K x) per level.
- *  coarsest_iters right-preconditioned GMRES(BJ) iterations on the coarsest level.
+ *  coarsest_iters right-preconditioned GMRES(BJ) iterations on the coarsest level
+ *                 (1..63).
  *  prec_fine      DG_FP64 or DG_FP32: storage/arithmetic of the level-0 PLU factors.
  *  prec_coarse    DG_FP64, DG_FP32 or DG_BF16: storage of the assembled coarse
  *                 operator blocks (BF16: rounded to nearest even, products
@@ -103,7 +104,7 @@ typedef struct {
     int coarse_matrix_free;
 } pmg_opts;
 
-/* FGMRES(restart) (Sec. 6): x0 = 0, converged when the recomputed true
+/* FGMRES(restart) (Sec. 6), restart 1..63: x0 = 0, converged when the recomputed true
  * residual ||b - K x|| <= rtol ||b||.  jvp_exact: 1 = tangent-linear Jacobian
  * action as the Krylov operator, 0 = the finite-difference form of Eq. DG-mf. */
 typedef struct {

@@ -267,16 +267,8 @@ void smooth(dg_ctx* ctx, int l, double* x, const double* b, int nu, bool x_zero)
 
 // Arnoldi step j with classical Gram-Schmidt applied twice; w is in V[j+1].
 void arnoldi_orth(dg_ctx* ctx, Krylov& K, int j, size_t n) {
-    double* w = K.V.p + (size_t)(j + 1) * n;
-    double* hcol = K.H.p + (size_t)j * (K.m + 1);
-    CK(launch_multi_dot(K.V.p, n, j + 1, w, n, ctx->partial.p, hcol, ctx->s));
-    CK(launch_multi_axpy(n, j + 1, hcol, -1, K.V.p, n, w, ctx->s));
-    CK(launch_multi_dot(K.V.p, n, j + 1, w, n, ctx->partial.p, K.h2.p, ctx->s));
-    CK(launch_multi_axpy(n, j + 1, K.h2.p, -1, K.V.p, n, w, ctx->s));
-    dot(ctx, w, w, n, K.sc.p + 0);
-    CK(launch_gs_finish(hcol, K.h2.p, j + 1, K.sc.p + 0, K.sc.p + 1, ctx->s));
-    CK(launch_scale_dev(n, w, K.sc.p + 1, 1, w, ctx->s));
-    CK(launch_givens(K.H.p, K.m + 1, j, K.cs.p, K.sn.p, K.g.p, K.sc.p + 2, ctx->s));
+    CK(launch_arnoldi_cgs2(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p, K.sc.p + 1, K.sc.p + 2,
+                           ctx->partial.p, ctx->s));
 }
 
 // Coarsest SOLVE: right-preconditioned GMRES(BJ) from x = 0 for exactly
@@ -374,7 +366,7 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
     for (int l = 1; l < o->n_levels; ++l)
         if (o->p_level[l] < 1 || o->p_level[l] >= o->p_level[l - 1])
             fail(ctx, DG_EINVAL, "coarse degrees must decrease and be >= 1");
-    if (o->nu_pre < 0 || o->nu_post < 0 || o->coarsest_iters < 1 || o->coarsest_iters > 200)
+    if (o->nu_pre < 0 || o->nu_post < 0 || o->coarsest_iters < 1 || o->coarsest_iters > 63)
         fail(ctx, DG_EINVAL, "bad sweep or coarsest iteration counts");
     if (o->prec_fine != DG_FP64 && o->prec_fine != DG_FP32) fail(ctx, DG_EINVAL, "prec_fine must be FP64 or FP32");
     if (o->prec_coarse != DG_FP64 && o->prec_coarse != DG_FP32 && o->prec_coarse != DG_BF16)
@@ -502,7 +494,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
 // ---- FGMRES (Sec. 6) --------------------------------------------------------------------
 void fgmres_impl(dg_ctx* ctx, const double* W, const double* RW, const double* b, double* x, const fgmres_opts* o,
                  fgmres_stats* st) {
-    if (!o || o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->rtol > 0.0))
+    if (!o || o->restart < 1 || o->restart > 63 || o->max_restarts < 0 || !(o->rtol > 0.0))
         fail(ctx, DG_EINVAL, "bad fgmres_opts");
     const size_t n = ctx->N;
     Krylov& K = ctx->kf;

@@ -95,6 +95,11 @@ hipError_t launch_restrict(int ne, int nvf, int nvc, const double* fine, double*
 hipError_t launch_prolong_add(int ne, int nvf, int nvc, const double* coarse, double* fine, int overwrite,
                               hipStream_t s);
 hipError_t launch_count_nonfinite(size_t n, const double* x, int* flag, hipStream_t s);
+// One Arnoldi step j (basis V[0..j], new vector in V[j+1]): classical
+// Gram-Schmidt twice, H column j, norm, Givens rotation j, normalisation;
+// est = |g_{j+1}|.  j + 1 <= 64.
+hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
+                               double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s);
 
 // ---- dense block kernels (lu_kernels.hip) ------------------------------------
 template <class TF>

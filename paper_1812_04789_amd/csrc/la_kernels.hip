@@ -290,4 +290,137 @@ hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---- fused classical Gram-Schmidt (applied twice) for one Arnoldi step -----------------------
+// Step j, w = V[j+1], basis V[0..j]:
+//   K1  part_a = partial sums of V_i . w             (i <= j)
+//   K2  h      = sum of part_a                         -> H column j
+//   K3  w     -= sum_i h_i V_i ; part_b = V_i . w      (second pass dots)
+//   K4  h2     = sum of part_b
+//   K5  w     -= sum_i h2_i V_i ; part_c = w . w
+//   K6  (one block) h += h2, H[j+1,j] = ||w||, Givens rotation j, |g_{j+1}|
+//   K7  w     /= ||w||
+// Every sum has a fixed order: the result depends only on the data.
+constexpr int GS_MAXK = 64;
+constexpr int GS_CH = 16;
+
+__global__ void __launch_bounds__(RED_THREADS)
+    gs_dots_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ w,
+                   double* __restrict__ part) {
+    __shared__ double sh[RED_THREADS];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int c0 = 0; c0 < k; c0 += GS_CH) {
+        double acc[GS_CH];
+#pragma unroll
+        for (int c = 0; c < GS_CH; ++c) acc[c] = 0.0;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < GS_CH; ++c)
+                if (c0 + c < k) acc[c] = fma(V[(size_t)(c0 + c) * n + i], wi, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < GS_CH; ++c)
+            if (c0 + c < k) {
+                const double sm = block_sum(acc[c], sh);
+                if (threadIdx.x == 0) part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = sm;
+            }
+    }
+}
+
+// w -= sum_i h_i V_i, then part = V_i . w (mode 0) or part = w . w (mode 1)
+__global__ void __launch_bounds__(RED_THREADS)
+    gs_update_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ h, double* __restrict__ w,
+                     double* __restrict__ part, int mode) {
+    __shared__ double sh[RED_THREADS];
+    __shared__ double hs[GS_MAXK];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) hs[i] = h[i];
+    __syncthreads();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    if (mode == 1) {
+        double nrm = 0.0;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            double wi = w[i];
+            for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
+            w[i] = wi;
+            nrm = fma(wi, wi, nrm);
+        }
+        const double sm = block_sum(nrm, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = sm;
+        return;
+    }
+    // mode 0: update, then dots with the updated w in chunks of GS_CH
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double wi = w[i];
+        for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
+        w[i] = wi;
+    }
+    for (int c0 = 0; c0 < k; c0 += GS_CH) {
+        double acc[GS_CH];
+#pragma unroll
+        for (int c = 0; c < GS_CH; ++c) acc[c] = 0.0;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < GS_CH; ++c)
+                if (c0 + c < k) acc[c] = fma(V[(size_t)(c0 + c) * n + i], wi, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < GS_CH; ++c)
+            if (c0 + c < k) {
+                const double sm = block_sum(acc[c], sh);
+                if (threadIdx.x == 0) part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = sm;
+            }
+    }
+}
+
+// One block: nrm2 = sum(part_c); hcol[i] += h2[i]; hcol[j+1] = ||w||; Givens j.
+__global__ void __launch_bounds__(RED_THREADS)
+    gs_finish_givens_kernel(const double* __restrict__ part, int nparts, double* H, int ldh, int j,
+                            const double* __restrict__ h2, double* cs, double* sn, double* g, double* nrm_out,
+                            double* est) {
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+    const double nrm2 = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    double* h = H + (size_t)j * ldh;
+    for (int i = 0; i <= j; ++i) h[i] += h2[i];
+    const double nr = sqrt(nrm2);
+    h[j + 1] = nr;
+    nrm_out[0] = nr;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double r = hypot(a, b);
+    const double c = (r > 0.0) ? a / r : 1.0, sg = (r > 0.0) ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = sg;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sg * g[j];
+    g[j] = c * g[j];
+    est[0] = fabs(g[j + 1]);
+}
+
+hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
+                               double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s) {
+    const int k = j + 1;
+    if (k > GS_MAXK) return hipErrorInvalidValue;
+    const int nbk = red_blocks(n);
+    double* w = const_cast<double*>(V) + (size_t)k * n;
+    double* hcol = H + (size_t)j * ldh;
+    hipLaunchKernelGGL(gs_dots_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, w, partial);
+    hipLaunchKernelGGL(sum_stage2, dim3(k), dim3(RED_THREADS), 0, s, partial, nbk, hcol);
+    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, hcol, w, partial, 0);
+    hipLaunchKernelGGL(sum_stage2, dim3(k), dim3(RED_THREADS), 0, s, partial, nbk, h2);
+    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, h2, w, partial, 1);
+    hipLaunchKernelGGL(gs_finish_givens_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, nbk, H, ldh, j, h2, cs, sn,
+                       g, nrm, est);
+    hipLaunchKernelGGL(scale_dev_kernel, grid_for(n), dim3(256), 0, s, n, w, nrm, 1, w);
+    return hipGetLastError();
+}
+
 }  // namespace dg
