@@ -223,10 +223,14 @@ dg_status dg_use_graphs(dg_ctx* ctx, int enable);
  * bytes and flops of those launches (what the operation must move/compute:
  * residual 16 B/DOF, FD J.v 32 B/DOF, exact J.v 24 B/DOF, diagonal blocks the
  * written blocks, PLU (2/3) n^3 flops and one read + write of the block,
- * block solve one read of the factors and 16 B per vector entry) since the
- * last clear, then clears.  All arrays have DG_K_COUNT entries (host memory). */
+ * block-Jacobi apply one read of the factors (or inverse) and 16 B per vector
+ * entry, block-sparse coarse product its 7 blocks per element and 16 B per
+ * entry, Arnoldi step j 32 (j + 1) B per entry: two passes of dots and
+ * updates) since the last clear, then clears.  The fine-level (level 0)
+ * block-Jacobi apply is its own family; coarse-level applies form another.
+ * All arrays have DG_K_COUNT entries (host memory). */
 enum { DG_K_RESIDUAL = 0, DG_K_JVP_FD = 1, DG_K_JVP_EXACT = 2, DG_K_DIAG_BLOCKS = 3, DG_K_LU = 4,
-       DG_K_LU_SOLVE = 5, DG_K_BSR = 6, DG_K_COUNT = 7 };
+       DG_K_BJ_FINE = 5, DG_K_BSR = 6, DG_K_BJ_COARSE = 7, DG_K_ARNOLDI = 8, DG_K_COUNT = 9 };
 dg_status dg_timing(dg_ctx* ctx, int enable);
 dg_status dg_timing_read(dg_ctx* ctx, double* ms, int* counts, double* bytes, double* flops);
 

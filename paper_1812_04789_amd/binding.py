@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdg_mi355x.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOCONV, DG_ENONFINITE, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
-KERNEL_KINDS = ["residual", "jvp_fd", "jvp_exact", "diag_blocks", "lu", "lu_solve", "bsr"]
+KERNEL_KINDS = ["residual", "jvp_fd", "jvp_exact", "diag_blocks", "lu", "bj_fine", "bsr", "bj_coarse", "arnoldi"]
 STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
           -5: "DG_ENONFINITE", -6: "DG_ESTATE"}
 

@@ -217,7 +217,8 @@ void jvp_fd(dg_ctx* ctx, const double* W, const double* RW, const double* v, dou
 void bj_apply(dg_ctx* ctx, int l, const double* r, double* z) {
     Level& L = ctx->lv[l];
     const double nbl = L.nb, sf = L.use32 ? 4.0 : 8.0;
-    timed(ctx, DG_K_LU_SOLVE, ctx->ne * (sf * nbl * nbl + 20.0 * nbl), ctx->ne * 2.0 * nbl * nbl, [&] {
+    timed(ctx, l == 0 ? DG_K_BJ_FINE : DG_K_BJ_COARSE, ctx->ne * (sf * nbl * nbl + 16.0 * nbl),
+          ctx->ne * 2.0 * nbl * nbl, [&] {
         if (L.inv)
             return L.use32 ? launch_inv_gemv<float>(L.inv32.p, r, z, ctx->ne, L.nb, ctx->s)
                            : launch_inv_gemv<double>(L.inv64.p, r, z, ctx->ne, L.nb, ctx->s);
@@ -267,8 +268,10 @@ void smooth(dg_ctx* ctx, int l, double* x, const double* b, int nu, bool x_zero)
 
 // Arnoldi step j with classical Gram-Schmidt applied twice; w is in V[j+1].
 void arnoldi_orth(dg_ctx* ctx, Krylov& K, int j, size_t n) {
-    CK(launch_arnoldi_cgs2(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p, K.sc.p + 1, K.sc.p + 2,
-                           ctx->partial.p, ctx->s));
+    timed(ctx, DG_K_ARNOLDI, 32.0 * (j + 1) * (double)n, 8.0 * (j + 1) * (double)n, [&] {
+        return launch_arnoldi_cgs2(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p, K.sc.p + 1,
+                                   K.sc.p + 2, ctx->partial.p, ctx->s);
+    });
 }
 
 // Coarsest SOLVE: right-preconditioned GMRES(BJ) from x = 0 for exactly

@@ -47,3 +47,14 @@ def test_null_arguments_rejected_without_gpu_work():
     assert lib.dg_ndof(None) == 0
     assert lib.dg_residual(None, None, None) == binding.DG_EINVAL
     assert lib.dg_batched_lu(None, None, None, 1, 4) == binding.DG_EINVAL
+
+
+def test_enums_match_header():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    kinds = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"DG_K_([A-Z0-9_]+)\s*=\s*(\d+)", src))
+    count = kinds.pop("COUNT")
+    assert len(binding.KERNEL_KINDS) == count
+    for name, i in kinds.items():
+        assert binding.KERNEL_KINDS[i] == name.lower()
+    prec = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"DG_(FP64|FP32|BF16)\s*=\s*(\d+)", src))
+    assert prec == {"FP64": binding.DG_FP64, "FP32": binding.DG_FP32, "BF16": binding.DG_BF16}
