@@ -234,6 +234,81 @@ enum { DG_K_RESIDUAL = 0, DG_K_JVP_FD = 1, DG_K_JVP_EXACT = 2, DG_K_DIAG_BLOCKS 
 dg_status dg_timing(dg_ctx* ctx, int enable);
 dg_status dg_timing_read(dg_ctx* ctx, double* ms, int* counts, double* bytes, double* flops);
 
+
+/* ---- Batches of independent cases -------------------------------------------
+ * A batch holds many independent cases (each its own periodic mesh, gas and
+ * degree p), one context per case on its own stream.  Batched vectors are the
+ * concatenation of the cases' vectors in case order: case c occupies
+ * dg_batch_ndof(b, c) entries from dg_batch_offset(b, c), each in the layout of
+ * a single context.  The DG operator of all cases (residual Sec. 3.1 Eq. re;
+ * FD product Sec. 5.1 Eq. DG-mf with a per-case step h_c computed from the
+ * case's own norms; exact product) runs as ONE persistent launch over a device
+ * work list of (case, element tile) items, each taking the compiled path of
+ * its degree; results equal the single-context calls bitwise.  Every case of a
+ * batch must share Euler/Navier-Stokes and straight/curved.  Calls enqueue on
+ * the batch stream hip_stream (NULL = the default stream); graphs are
+ * captured on a private stream and launched on the batch stream. */
+typedef struct dg_batch dg_batch;
+
+typedef struct {
+    dg_mesh_desc mesh;
+    dg_phys phys;
+    int p;
+} dg_case_desc;
+
+/* Tile shape of one batched kernel kind: workgroup size, elements per
+ * workgroup for each degree (epb[1..4]; 0 = degree absent), persistent grid,
+ * dynamic LDS bytes, measured ms per launch (-1 if not tuned), candidates
+ * timed by the autotuner and work items. */
+typedef struct {
+    int threads;
+    int epb[5];
+    int grid;
+    size_t lds_bytes;
+    double ms;
+    int candidates;
+    int items;
+} dg_batch_tile;
+
+dg_status dg_batch_create(const dg_case_desc* cases, int ncases, void* hip_stream, dg_batch** out);
+dg_status dg_batch_destroy(dg_batch* b);
+const char* dg_batch_last_error(const dg_batch* b);
+/* Entries of case c (c < 0: the whole batch) and its first entry. */
+size_t dg_batch_ndof(const dg_batch* b, int c);
+size_t dg_batch_offset(const dg_batch* b, int c);
+/* The context of case c (owned by the batch; valid until dg_batch_destroy):
+ * every single-context entry point can be used on it, on the case's stream. */
+dg_ctx* dg_batch_case(dg_batch* b, int c);
+/* R = R(W) for every case (Sec. 3.1 Eq. re). */
+dg_status dg_batch_residual(dg_batch* b, const double* W, double* R);
+/* y_c = shift M v_c + (R(W_c + h_c v_c) - RW_c) / h_c,
+ * h_c = 1e-7 sqrt(1 + ||W_c||) / ||v_c|| (Sec. 5.1 Eq. DG-mf).  Replayed as a
+ * HIP graph when called again with the same pointers and shift. */
+dg_status dg_batch_jvp(dg_batch* b, const double* W, const double* RW, const double* v, double shift, double* y);
+/* y_c = shift M v_c + J(W_c) v_c exactly (tangent-linear). */
+dg_status dg_batch_jvp_exact(dg_batch* b, const double* W, const double* v, double shift, double* y);
+dg_status dg_batch_use_graphs(dg_batch* b, int enable);
+/* kind: DG_K_RESIDUAL, DG_K_JVP_FD or DG_K_JVP_EXACT. */
+dg_status dg_batch_get_tile(dg_batch* b, int kind, dg_batch_tile* t);
+/* Fix a tile shape: threads 64..256 (multiple of 64), LDS cap in bytes (a
+ * degree whose element slot needs more still gets one element), persistent
+ * grid of grid_per_cu workgroups per CU (at most the number of items). */
+dg_status dg_batch_set_tile(dg_batch* b, int kind, int threads, size_t lds_cap, int grid_per_cu);
+/* Autotuner: time every candidate shape (threads 64/128/192/256, LDS caps
+ * 32/64/96/160 KB, 1/2/4/8 workgroups per CU) on the given operands, `reps`
+ * launches each, and keep the fastest for this kind (chosen may be NULL).
+ * RW is needed for DG_K_JVP_FD, v for both products.  Synchronises. */
+dg_status dg_batch_tune(dg_batch* b, int kind, const double* W, const double* RW, const double* v, int reps,
+                        dg_batch_tile* chosen);
+/* One BDF2 step (as dg_bdf2_step) of every case: popts[c] is case c's
+ * preconditioner, fopts/newton_rtol/max_newton are shared, stats[c] (may be
+ * NULL) receives case c's statistics.  `workers` host threads run the cases,
+ * largest first, each on its own stream.  Synchronous.  Returns DG_ENOCONV
+ * (all steps completed) if some case missed its tolerance. */
+dg_status dg_batch_bdf2_step(dg_batch* b, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
+                             const fgmres_opts* fopts, double newton_rtol, int max_newton, int workers, double* Wnp1,
+                             dg_step_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,16 @@ class StepStats(ctypes.Structure):
                 ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
 
 
+class CaseDesc(ctypes.Structure):
+    _fields_ = [("mesh", MeshDesc), ("phys", Phys), ("p", ctypes.c_int)]
+
+
+class BatchTile(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int), ("epb", ctypes.c_int * 5), ("grid", ctypes.c_int),
+                ("lds_bytes", ctypes.c_size_t), ("ms", ctypes.c_double), ("candidates", ctypes.c_int),
+                ("items", ctypes.c_int)]
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -78,7 +88,23 @@ SIGNATURES = {
     "dg_timing_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "dg_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
                           ctypes.POINTER(StepStats)]),
+    "dg_batch_create": (_I, [ctypes.POINTER(CaseDesc), _I, _P, ctypes.POINTER(_P)]),
+    "dg_batch_destroy": (_I, [_P]),
+    "dg_batch_last_error": (ctypes.c_char_p, [_P]),
+    "dg_batch_ndof": (ctypes.c_size_t, [_P, _I]),
+    "dg_batch_offset": (ctypes.c_size_t, [_P, _I]),
+    "dg_batch_case": (_P, [_P, _I]),
+    "dg_batch_residual": (_I, [_P, _P, _P]),
+    "dg_batch_jvp": (_I, [_P, _P, _P, _P, _D, _P]),
+    "dg_batch_jvp_exact": (_I, [_P, _P, _P, _D, _P]),
+    "dg_batch_use_graphs": (_I, [_P, _I]),
+    "dg_batch_get_tile": (_I, [_P, _I, ctypes.POINTER(BatchTile)]),
+    "dg_batch_set_tile": (_I, [_P, _I, _I, ctypes.c_size_t, _I]),
+    "dg_batch_tune": (_I, [_P, _I, _P, _P, _P, _I, ctypes.POINTER(BatchTile)]),
+    "dg_batch_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _I,
+                                _P, ctypes.POINTER(StepStats)]),
 }
+KIND = {name: i for i, name in enumerate(KERNEL_KINDS)}
 
 _lib = None
 
@@ -132,11 +158,22 @@ class Context:
     gamma, mu (0 = Euler), Pr, eta: gas model and BR2 penalty;
     vertices: optional host float64 array (ne, 8, 3) of Q1 vertices."""
 
-    def __init__(self, n, lo, hi, p, gamma=1.4, mu=0.0, Pr=0.72, eta=7.0, vertices=None, stream=None):
+    def __init__(self, n, lo, hi, p, gamma=1.4, mu=0.0, Pr=0.72, eta=7.0, vertices=None, stream=None, _borrow=None):
         import numpy as np
         import torch
         self.torch = torch
         self.lib = load()
+        self.owned = _borrow is None
+        self.sync = not self.owned
+        if _borrow is not None:        # a context owned by a Batch (runs on the case's own stream)
+            self.h = ctypes.c_void_p(_borrow)
+            self.stream = None
+            self.n, self.p = tuple(int(x) for x in n), int(p)
+            self.ne = self.n[0] * self.n[1] * self.n[2]
+            self.nv = (self.p + 1) ** 3
+            self.ndof = int(self.lib.dg_ndof(self.h))
+            self.device = torch.device("cuda", torch.cuda.current_device())
+            return
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -165,7 +202,8 @@ class Context:
     # ---- helpers -------------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
-            self.lib.dg_destroy(self.h)
+            if self.owned:
+                self.lib.dg_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -177,9 +215,13 @@ class Context:
     def _check(self, st):
         if st != DG_OK:
             raise DGError(st, self.lib.dg_last_error(self.h).decode())
+        if self.sync:                  # borrowed context: its stream is not torch's
+            self.torch.cuda.synchronize()
 
     def _vec(self, t, name, n=None):
         torch = self.torch
+        if self.sync:                  # borrowed context: inputs written on torch's stream must be ready
+            torch.cuda.synchronize()
         n = self.ndof if n is None else n
         if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
                 and t.numel() == n):
@@ -298,3 +340,134 @@ def batched_lu_solve(LU, piv, b, x, stream=None):
     st = lib.dg_batched_lu_solve(ctypes.c_void_p(s.cuda_stream), _ptr(LU), _ptr(piv), _ptr(b), _ptr(x), nblk, n)
     if st != DG_OK:
         raise DGError(st, "dg_batched_lu_solve")
+
+
+class Batch:
+    """Many independent cases on the current device (dg_batch_* entry points).
+
+    cases: list of dicts with keys n, lo, hi, p and optional gamma, mu, Pr,
+    eta, vertices.  Batched vectors concatenate the cases' vectors in order;
+    `split` returns per-case views."""
+
+    def __init__(self, cases, stream=None):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (CaseDesc * len(cases))()
+        self._keep = []
+        for i, c in enumerate(cases):
+            d = arr[i]
+            d.mesh.nx, d.mesh.ny, d.mesh.nz = (int(x) for x in c["n"])
+            for k in range(3):
+                d.mesh.lo[k] = float(c["lo"][k])
+                d.mesh.hi[k] = float(c["hi"][k])
+            if c.get("vertices") is not None:
+                v = np.ascontiguousarray(c["vertices"], dtype=np.float64)
+                self._keep.append(v)
+                d.mesh.vtx = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.phys = Phys(c.get("gamma", 1.4), c.get("mu", 0.0), c.get("Pr", 0.72), c.get("eta", 7.0))
+            d.p = int(c["p"])
+        h = ctypes.c_void_p()
+        st = self.lib.dg_batch_create(arr, len(cases), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != DG_OK:
+            raise DGError(st, "dg_batch_create failed")
+        self.h = h
+        self.cases = [dict(c) for c in cases]
+        self.nc = len(cases)
+        self.ndof = int(self.lib.dg_batch_ndof(h, -1))
+        self.sizes = [int(self.lib.dg_batch_ndof(h, i)) for i in range(self.nc)]
+        self.offsets = [int(self.lib.dg_batch_offset(h, i)) for i in range(self.nc)]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ok=(DG_OK,)):
+        if st not in ok:
+            raise DGError(st, self.lib.dg_batch_last_error(self.h).decode())
+        return st
+
+    def _vec(self, t, name):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                and t.numel() == self.ndof):
+            raise ValueError("%s must be a contiguous float64 CUDA tensor with %d entries" % (name, self.ndof))
+        return _ptr(t)
+
+    def empty(self):
+        return self.torch.empty(self.ndof, dtype=self.torch.float64, device=self.device)
+
+    def split(self, t):
+        return [t[o:o + n] for o, n in zip(self.offsets, self.sizes)]
+
+    def case(self, c):
+        """The case's own context (borrowed: single-context calls on the case's stream)."""
+        h = self.lib.dg_batch_case(self.h, int(c))
+        cd = self.cases[c]
+        return Context(cd["n"], cd["lo"], cd["hi"], cd["p"], _borrow=h)
+
+    def residual(self, W, R=None):
+        R = self.empty() if R is None else R
+        self._check(self.lib.dg_batch_residual(self.h, self._vec(W, "W"), self._vec(R, "R")))
+        return R
+
+    def jvp(self, W, RW, v, shift, y=None):
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_batch_jvp(self.h, self._vec(W, "W"), self._vec(RW, "RW"), self._vec(v, "v"),
+                                          float(shift), self._vec(y, "y")))
+        return y
+
+    def jvp_exact(self, W, v, shift, y=None):
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_batch_jvp_exact(self.h, self._vec(W, "W"), self._vec(v, "v"), float(shift),
+                                                self._vec(y, "y")))
+        return y
+
+    def use_graphs(self, enable):
+        self._check(self.lib.dg_batch_use_graphs(self.h, 1 if enable else 0))
+
+    @staticmethod
+    def _tile_dict(t):
+        return dict(threads=t.threads, epb=list(t.epb)[1:], grid=t.grid, lds_bytes=int(t.lds_bytes), ms=t.ms,
+                    candidates=t.candidates, items=t.items)
+
+    def tile(self, kind):
+        t = BatchTile()
+        self._check(self.lib.dg_batch_get_tile(self.h, KIND[kind], ctypes.byref(t)))
+        return self._tile_dict(t)
+
+    def set_tile(self, kind, threads, lds_cap, grid_per_cu):
+        self._check(self.lib.dg_batch_set_tile(self.h, KIND[kind], int(threads), int(lds_cap), int(grid_per_cu)))
+
+    def tune(self, kind, W, RW=None, v=None, reps=3):
+        t = BatchTile()
+        self._check(self.lib.dg_batch_tune(self.h, KIND[kind], self._vec(W, "W"),
+                                           self._vec(RW, "RW") if RW is not None else None,
+                                           self._vec(v, "v") if v is not None else None, int(reps),
+                                           ctypes.byref(t)))
+        return self._tile_dict(t)
+
+    def bdf2_step(self, Wn, Wnm1, dt, popts, fopts, newton_rtol=1e-10, max_newton=5, workers=8, Wnp1=None,
+                  raise_on_noconv=True):
+        """popts: one pmg_opts per case.  Returns (Wnp1, [StepStats], status)."""
+        Wnp1 = self.empty() if Wnp1 is None else Wnp1
+        po = (PmgOpts * self.nc)(*popts)
+        st = (StepStats * self.nc)()
+        wm = self._vec(Wnm1, "Wnm1") if Wnm1 is not None else None
+        s = self.lib.dg_batch_bdf2_step(self.h, self._vec(Wn, "Wn"), wm, float(dt), po, ctypes.byref(fopts),
+                                        float(newton_rtol), int(max_newton), int(workers), self._vec(Wnp1, "Wnp1"),
+                                        st)
+        self._check(s, (DG_OK,) if raise_on_noconv else (DG_OK, DG_ENOCONV))
+        return Wnp1, list(st), s

@@ -142,6 +142,10 @@ struct dg_ctx {
     size_t ev_used = 0;
 };
 
+namespace dg {
+const DGArgs& ctx_args(const dg_ctx* ctx) { return ctx->a; }
+}  // namespace dg
+
 namespace {
 
 // scalar slots in ctx->scal

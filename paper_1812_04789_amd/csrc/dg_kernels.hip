@@ -96,7 +96,6 @@ struct Sz {
     static constexpr int TOT = OFF_F + 120 * NF;
 };
 
-enum { M_RES = 0, M_JVP_FD = 1, M_TANGENT = 2, M_DIAGCOL = 3 };
 
 template <int P, bool DUAL>
 struct Launch;
@@ -140,19 +139,17 @@ __device__ __forceinline__ void sweep(const double (*Tb)[MAXN], const T* src, T*
     }
 }
 
-// Load one modal coefficient of element el as the kernel's scalar type.
+// Load one modal coefficient as the kernel's scalar type: W (residual),
+// W + h v (FD product) or the dual number (W, v) (exact product).
 template <int MODE, class T>
-__device__ __forceinline__ T load_state(const double* W, const double* v, double h, size_t off, int local, int col,
-                                        bool tangent_on) {
+__device__ __forceinline__ T load_state(const double* W, const double* v, double h, size_t off) {
     const double w = W[off];
     if constexpr (MODE == M_RES) {
         return w;
     } else if constexpr (MODE == M_JVP_FD) {
         return w + h * v[off];
-    } else if constexpr (MODE == M_TANGENT) {
-        return mk<T>(w, v[off]);
     } else {
-        return mk<T>(w, (tangent_on && local == col) ? 1.0 : 0.0);
+        return mk<T>(w, v[off]);
     }
 }
 
@@ -208,27 +205,22 @@ __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3],
     }
 }
 
-template <int P, bool NS, bool CURVED, int MODE>
-__global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ))
-    dg_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ V,
-              const double* __restrict__ RW, const double* __restrict__ hbuf, double shift,
-              double* __restrict__ out) {
+// One element of the DG operator (residual, FD product or exact product),
+// evaluated by the NQ threads of one element slot, thread q at Gauss point q.
+// S: the slot's LDS scratch (Sz<P>::TOT scalars), sdet: NQ doubles, svtx: 24
+// doubles.  Every thread of the workgroup calls this together (barriers);
+// threads of an inactive slot (no element) pass active = false.
+template <int P, bool NS, bool CURVED, int MODE,
+          class T = typename std::conditional<(MODE >= M_TANGENT), Dual, double>::type>
+__device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, const double* __restrict__ W,
+                                           const double* __restrict__ V, const double* __restrict__ RW,
+                                           const double* __restrict__ hbuf, double shift, double* __restrict__ out,
+                                           T* S, double* sdet, double* svtx, int e, bool active, int q) {
     using S_ = Sz<P>;
     constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = S_::NB;
     constexpr bool DUAL = (MODE >= M_TANGENT);
-    using T = typename std::conditional<DUAL, Dual, double>::type;
-    constexpr int EPB = Launch<P, DUAL>::EPB;
-    __shared__ T smem[EPB * S_::TOT];
-    __shared__ double sdet[EPB][NQ];
-    __shared__ double svtx[EPB][24];
-
     const Tab& tb = c_tab[P];
     const short* perm = c_perm + perm_offset(P);
-    const int tid = threadIdx.x;
-    const int es = tid / NQ, q = tid % NQ;
-    const int e = blockIdx.x * EPB + es;
-    const bool active = e < m.ne;
-    const int col = (MODE == M_DIAGCOL) ? (int)blockIdx.y : -1;
     double h = 0.0;
     if constexpr (MODE == M_JVP_FD) {
         h = hbuf[0];
@@ -238,7 +230,6 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
             return;
         }
     }
-    T* S = smem + es * S_::TOT;
     const int ii[3] = {q / NF, (q / N) % N, q % N};
 
     // ---- load own modal coefficients (tensor order) --------------------------------
@@ -247,9 +238,9 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
         const int pm = perm[q];
 #pragma unroll
         for (int a = 0; a < 5; ++a)
-            S[a * NQ + q] = load_state<MODE, T>(W, V, h, base + a * NQ + pm, a * NQ + pm, col, true);
+            S[a * NQ + q] = load_state<MODE, T>(W, V, h, base + a * NQ + pm);
         if constexpr (CURVED)
-            for (int k = q; k < 24; k += NQ) svtx[es][k] = m.vtx[(size_t)e * 24 + k];
+            for (int k = q; k < 24; k += NQ) svtx[k] = m.vtx[(size_t)e * 24 + k];
     }
     __syncthreads();
     // ---- interpolation to the Gauss points ---------------------------------------
@@ -284,9 +275,9 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
         }
         if constexpr (CURVED) {
             double J[3][3];
-            q1_jac(svtx[es], tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
+            q1_jac(svtx, tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
             detJ = q1_inv(J, Ji);
-            sdet[es][q] = detJ;
+            sdet[q] = detJ;
         } else {
             detJ = 0.125 * hx * hy * hz;
 #pragma unroll
@@ -339,7 +330,7 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
                     const int pm = perm[tb0 + k * sd];
-                    const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm, a * NQ + pm, col, nb == e);
+                    const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm);
                     c0 = fma(tb.Le[1 - s][k], val, c0);
                     c1 = fma(tb.Lde[1 - s][k], val, c1);
                 }
@@ -422,7 +413,7 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
 #pragma unroll
                 for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
                 double J[3][3];
-                q1_jac(svtx[es], xi[0], xi[1], xi[2], J);
+                q1_jac(svtx, xi[0], xi[1], xi[2], J);
                 q1_inv(J, Jip);
                 // tangents dx/dxi_{d+1}, dx/dxi_{d+2} (cyclic): their cross product points to +xi_d
                 const int da = (d + 1) % 3, db = (d + 2) % 3;
@@ -446,7 +437,7 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
                 q1_inv(J, Jim);
                 double sp = 0.0, sm = 0.0;
                 for (int k = 0; k < N; ++k) {
-                    sp += tb.br2[s][k] / sdet[es][tl + k * sd];
+                    sp += tb.br2[s][k] / sdet[tl + k * sd];
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
                     q1_jac(vn, xi[0], xi[1], xi[2], J);
@@ -548,10 +539,6 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
         if (active)
 #pragma unroll
             for (int a = 0; a < 5; ++a) out[base + a * NQ + pm] = tan_(res[a]);
-    } else if constexpr (MODE == M_DIAGCOL) {
-        if (active)
-#pragma unroll
-            for (int a = 0; a < 5; ++a) out[((size_t)e * NB + col) * NB + a * NQ + pm] = tan_(res[a]);
     } else {
         // y = shift M v + (R(W + h v) - R(W)) / h
         double mv[5];
@@ -601,6 +588,25 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
             }
         }
     }
+}
+
+template <int P, bool NS, bool CURVED, int MODE>
+__global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ))
+    dg_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ V,
+              const double* __restrict__ RW, const double* __restrict__ hbuf, double shift,
+              double* __restrict__ out) {
+    using S_ = Sz<P>;
+    constexpr int NQ = S_::NQ;
+    constexpr bool DUAL = (MODE >= M_TANGENT);
+    using T = typename std::conditional<DUAL, Dual, double>::type;
+    constexpr int EPB = Launch<P, DUAL>::EPB;
+    __shared__ T smem[EPB * S_::TOT];
+    __shared__ double sdet[EPB][NQ];
+    __shared__ double svtx[EPB][24];
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const int e = blockIdx.x * EPB + es;
+    dg_element<P, NS, CURVED, MODE>(m, gas, W, V, RW, hbuf, shift, out, smem + es * S_::TOT, sdet[es], svtx[es], e,
+                                    e < m.ne, q);
 }
 
 // ---- mass matrix, projection, quadrature points, Jacobian check --------------------------
@@ -741,7 +747,7 @@ hipError_t launch_dg(const DGArgs& a, const double* W, const double* V, const do
     constexpr bool DUAL = MODE >= M_TANGENT;
     constexpr int EPB = Launch<P, DUAL>::EPB;
     constexpr int NQ = Sz<P>::NQ;
-    dim3 grid((a.m.ne + EPB - 1) / EPB, MODE == M_DIAGCOL ? Sz<P>::NB : 1);
+    dim3 grid((a.m.ne + EPB - 1) / EPB);
     dim3 block(EPB * NQ);
     const bool curved = a.m.vtx != nullptr;
     if (a.ns) {
@@ -835,6 +841,100 @@ hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// ---- batched DG operator: one persistent launch over many cases ---------------------------
+// Work item = (case, first element, degree, elements in the tile).  Each
+// workgroup walks the item list with a fixed stride (item i goes to workgroup
+// i mod grid), runs the degree's compile-time path on its tile (one slot of
+// NQ threads per element) and moves on; results are per element, so they do
+// not depend on the tiling or the grid.
+size_t batch_slot_bytes(int p, int mode) {
+    const size_t sc = (mode == M_TANGENT) ? sizeof(Dual) : sizeof(double);
+    switch (p) {
+        case 1: return Sz<1>::TOT * sc + (Sz<1>::NQ + 24) * sizeof(double);
+        case 2: return Sz<2>::TOT * sc + (Sz<2>::NQ + 24) * sizeof(double);
+        case 3: return Sz<3>::TOT * sc + (Sz<3>::NQ + 24) * sizeof(double);
+        case 4: return Sz<4>::TOT * sc + (Sz<4>::NQ + 24) * sizeof(double);
+        default: return 0;
+    }
+}
+
+template <int P, bool NS, bool CURVED, int MODE>
+__device__ __forceinline__ void batch_tile(const BatchCaseDev& c, const BatchItem& w, double* dyn,
+                                           const double* __restrict__ W, const double* __restrict__ V,
+                                           const double* __restrict__ RW, const double* __restrict__ hcase,
+                                           double shift, double* __restrict__ out) {
+    using S_ = Sz<P>;
+    constexpr int NQ = S_::NQ;
+    using T = typename std::conditional<(MODE >= M_TANGENT), Dual, double>::type;
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const bool slot = es < w.n;
+    const int esl = slot ? es : 0;
+    T* S = reinterpret_cast<T*>(dyn) + (size_t)esl * S_::TOT;
+    double* sdet = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * S_::TOT) + esl * NQ;
+    double* svtx = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * S_::TOT) + w.n * NQ + esl * 24;
+    const size_t o = c.off;
+    const int e = w.e0 + es;
+    dg_element<P, NS, CURVED, MODE>(c.m, c.g, W + o, V ? V + o : nullptr, RW ? RW + o : nullptr, hcase + w.c, shift,
+                                    out + o, S, sdet, svtx, e, slot && e < c.m.ne, q);
+}
+
+template <bool NS, bool CURVED, int MODE>
+__global__ void __launch_bounds__(BATCH_MAX_THREADS)
+    batch_dg_kernel(const BatchCaseDev* __restrict__ cases, const BatchItem* __restrict__ items, int nitems,
+                    const double* __restrict__ W, const double* __restrict__ V, const double* __restrict__ RW,
+                    const double* __restrict__ hcase, double shift, double* __restrict__ out) {
+    extern __shared__ double dyn[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchCaseDev c = cases[w.c];
+        switch (w.p) {
+            case 1: batch_tile<1, NS, CURVED, MODE>(c, w, dyn, W, V, RW, hcase, shift, out); break;
+            case 2: batch_tile<2, NS, CURVED, MODE>(c, w, dyn, W, V, RW, hcase, shift, out); break;
+            case 3: batch_tile<3, NS, CURVED, MODE>(c, w, dyn, W, V, RW, hcase, shift, out); break;
+            default: batch_tile<4, NS, CURVED, MODE>(c, w, dyn, W, V, RW, hcase, shift, out); break;
+        }
+        __syncthreads();     // the next item reuses the LDS
+    }
+}
+
+namespace {
+template <bool NS, bool CURVED, int MODE>
+hipError_t launch_batch_dg_t(const BatchCaseDev* cases, const BatchItem* items, int nitems, int threads, int grid,
+                             size_t lds, const double* W, const double* V, const double* RW, const double* hcase,
+                             double shift, double* out, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void*)batch_dg_kernel<NS, CURVED, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_dg_kernel<NS, CURVED, MODE>), dim3(grid), dim3(threads), lds, s, cases, items, nitems,
+                       W, V, RW, hcase, shift, out);
+    return hipGetLastError();
+}
+template <int MODE>
+hipError_t launch_batch_dg_m(bool ns, bool curved, const BatchCaseDev* cases, const BatchItem* items, int nitems,
+                             int threads, int grid, size_t lds, const double* W, const double* V, const double* RW,
+                             const double* hcase, double shift, double* out, hipStream_t s) {
+    if (ns) {
+        if (curved) return launch_batch_dg_t<true, true, MODE>(cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+        return launch_batch_dg_t<true, false, MODE>(cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+    }
+    if (curved) return launch_batch_dg_t<false, true, MODE>(cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+    return launch_batch_dg_t<false, false, MODE>(cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+}
+}  // namespace
+
+hipError_t launch_batch_dg(int mode, bool ns, bool curved, const BatchCaseDev* cases, const BatchItem* items,
+                           int nitems, int threads, int grid, size_t lds, const double* W, const double* V,
+                           const double* RW, const double* hcase, double shift, double* out, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (threads < 64 || threads > BATCH_MAX_THREADS || threads % 64 || grid < 1) return hipErrorInvalidValue;
+    switch (mode) {
+        case M_RES: return launch_batch_dg_m<M_RES>(ns, curved, cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+        case M_JVP_FD: return launch_batch_dg_m<M_JVP_FD>(ns, curved, cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+        case M_TANGENT: return launch_batch_dg_m<M_TANGENT>(ns, curved, cases, items, nitems, threads, grid, lds, W, V, RW, hcase, shift, out, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ---- inherited coarse operators (Sec. 6.1) ---------------------------------------------------

@@ -72,7 +72,44 @@ hipError_t launch_quad_points(const DGArgs& a, double* xyz, hipStream_t s);
 hipError_t launch_project(const DGArgs& a, const double* vals, double* W, hipStream_t s);
 hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s);
 
+// Mesh and gas of a context (capi.cpp), for the batch layer.
+const DGArgs& ctx_args(const dg_ctx* ctx);
+
+// ---- batched DG operator (dg_kernels.hip) ------------------------------------
+enum { M_RES = 0, M_JVP_FD = 1, M_TANGENT = 2 };     // residual, FD product, exact product
+constexpr int BATCH_MAX_THREADS = 256;
+struct BatchCaseDev {
+    MeshDev m;
+    Gas g;
+    size_t off;               // first entry of the case in the batched vectors
+};
+struct BatchItem {
+    int c;                    // case
+    int e0;                   // first element of the tile
+    int p;                    // degree of the case (selects the compiled path)
+    int n;                    // elements in the tile (slots of (p+1)^3 threads)
+};
+// LDS bytes of one element slot of degree p for mode M_*.
+size_t batch_slot_bytes(int p, int mode);
+// One persistent launch: workgroup b runs items b, b + grid, ...; hcase[c] is
+// case c's FD step (M_JVP_FD).  Every case must share (ns, curved).
+hipError_t launch_batch_dg(int mode, bool ns, bool curved, const BatchCaseDev* cases, const BatchItem* items,
+                           int nitems, int threads, int grid, size_t lds, const double* W, const double* V,
+                           const double* RW, const double* hcase, double shift, double* out, hipStream_t s);
+
 // ---- vector / reduction kernels (la_kernels.hip) ----------------------------
+// Blocks of the deterministic reduction of n entries.
+int red_blocks_for(size_t n);
+// Per-case FD steps of a batch: block b of the first stage sums entries
+// lb, lb + nbk*256, ... of case c (offset off, length n), as the single-case
+// reduction does; h[c] = eps sqrt(1 + ||W_c||) / ||v_c|| (0 if v_c = 0).
+struct SegBlock {
+    int c, lb, nbk, pad;
+    size_t off, n;
+};
+hipError_t launch_seg_fd_step(const SegBlock* tab, int nblocks, const int* first, const int* nbk, int ncases,
+                              const double* W, const double* v, double* px, double* py, double eps, double* h,
+                              hipStream_t s);
 // Deterministic sums: fixed grid, fixed per-block order, fixed second stage.
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;

@@ -423,4 +423,57 @@ hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int 
     return hipGetLastError();
 }
 
+// ---- per-case FD steps of a batch ------------------------------------------------------------
+// Case c's squared norms are summed exactly as the single-case reduction of
+// its n_c entries (red_blocks(n_c) blocks, the same grid stride, the same
+// trees), so the step h_c is bitwise the one a single-case product uses.
+int red_blocks_for(size_t n) { return red_blocks(n); }
+
+__global__ void __launch_bounds__(RED_THREADS)
+    seg_sq_stage1(const SegBlock* __restrict__ tab, const double* __restrict__ x, const double* __restrict__ y,
+                  double* __restrict__ px, double* __restrict__ py) {
+    __shared__ double sh[RED_THREADS];
+    const SegBlock b = tab[blockIdx.x];
+    const size_t stride = (size_t)b.nbk * blockDim.x;
+    double ax = 0.0, ay = 0.0;
+    for (size_t i = (size_t)b.lb * blockDim.x + threadIdx.x; i < b.n; i += stride) {
+        const double xi = x[b.off + i], yi = y[b.off + i];
+        ax = fma(xi, xi, ax);
+        ay = fma(yi, yi, ay);
+    }
+    const double sx = block_sum(ax, sh);
+    const double sy = block_sum(ay, sh);
+    if (threadIdx.x == 0) {
+        px[blockIdx.x] = sx;
+        py[blockIdx.x] = sy;
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+    seg_fd_step(const int* __restrict__ first, const int* __restrict__ nbk, const double* __restrict__ px,
+                const double* __restrict__ py, double eps, double* __restrict__ h) {
+    __shared__ double sh[RED_THREADS];
+    const int c = blockIdx.x;
+    const double* a = px + first[c];
+    const double* b = py + first[c];
+    double ax = 0.0, ay = 0.0;
+    for (int i = threadIdx.x; i < nbk[c]; i += blockDim.x) ax += a[i];
+    for (int i = threadIdx.x; i < nbk[c]; i += blockDim.x) ay += b[i];
+    const double nw2 = block_sum(ax, sh);
+    const double nv2 = block_sum(ay, sh);
+    if (threadIdx.x == 0) {
+        const double nv = sqrt(nv2);
+        h[c] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2)) / nv : 0.0;
+    }
+}
+
+hipError_t launch_seg_fd_step(const SegBlock* tab, int nblocks, const int* first, const int* nbk, int ncases,
+                              const double* W, const double* v, double* px, double* py, double eps, double* h,
+                              hipStream_t s) {
+    if (nblocks <= 0 || ncases <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seg_sq_stage1, dim3(nblocks), dim3(RED_THREADS), 0, s, tab, W, v, px, py);
+    hipLaunchKernelGGL(seg_fd_step, dim3(ncases), dim3(RED_THREADS), 0, s, first, nbk, px, py, eps, h);
+    return hipGetLastError();
+}
+
 }  // namespace dg

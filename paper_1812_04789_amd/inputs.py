@@ -99,16 +99,34 @@ def fourier_phases(seed, kmax=4):
     return np.array(ks, float), rng.uniform(0.0, 2 * math.pi, size=(len(ks), 3))
 
 
+def _fourier_raw(y, ks, phases, L):
+    """sum_k cos(k.y 2pi/L + phi_{k,c}) for c = 0, 1, 2, evaluated as the real
+    part of sum_k e^{i phi} e^{i k1 y1'} e^{i k2 y2'} e^{i k3 y3'}, contracted
+    one axis at a time (same sum, far fewer transcendental evaluations)."""
+    y = np.asarray(y, float).reshape(-1, 3) * (2 * math.pi / L)
+    ki = ks.astype(int)
+    kmax = int(np.abs(ki).max())
+    m = 2 * kmax + 1
+    ax = np.arange(-kmax, kmax + 1)
+    E = [np.exp(1j * np.outer(y[:, d], ax)) for d in range(3)]       # (npts, m) per axis
+    out = np.empty((y.shape[0], 3))
+    for c in range(3):
+        C = np.zeros((m, m, m), complex)
+        C[ki[:, 0] + kmax, ki[:, 1] + kmax, ki[:, 2] + kmax] = np.exp(1j * phases[:, c])
+        t = E[2] @ C.reshape(m * m, m).T                                  # (npts, m*m): sum over k3
+        t = np.einsum('pab,pb->pa', t.reshape(-1, m, m), E[1])            # sum over k2
+        out[:, c] = np.einsum('pa,pa->p', t, E[0]).real                   # sum over k1
+    return out
+
+
 def fourier_velocity(x, ks, phases, amp=0.1, L=2 * math.pi):
     """sum_k cos(k.x 2pi/L + phi_{k,c}) per component, scaled so that its RMS
     over a uniform 16^3 sample grid of the box is `amp`."""
-    def raw(y):
-        arg = np.einsum('...d,kd->...k', y, ks) * (2 * math.pi / L)
-        return np.stack([np.cos(arg + phases[:, c]).sum(-1) for c in range(3)], axis=-1)
+    x = np.asarray(x, float)
     g = (np.arange(16) + 0.5) * L / 16
     G = np.stack(np.meshgrid(g, g, g, indexing='ij'), axis=-1).reshape(-1, 3)
-    rms = math.sqrt(float(np.mean(np.sum(raw(G) ** 2, axis=-1))))
-    return raw(np.asarray(x, float)) * (amp / rms)
+    rms = math.sqrt(float(np.mean(np.sum(_fourier_raw(G, ks, phases, L) ** 2, axis=-1))))
+    return (_fourier_raw(x, ks, phases, L) * (amp / rms)).reshape(x.shape)
 
 
 def fourier_state(x, ks, phases, gamma=1.4, mach=0.3, amp=0.1):
@@ -116,6 +134,39 @@ def fourier_state(x, ks, phases, gamma=1.4, mach=0.3, amp=0.1):
     rho = np.ones(x.shape[:-1])
     p = np.full(x.shape[:-1], 1.0 / (gamma * mach * mach))
     return conserved(rho, fourier_velocity(x, ks, phases, amp), p, gamma)
+
+
+# ---- batch and serving workloads ------------------------------------------------
+def batch_cases(count=96, seed=1812, nmin=4, nmax=12, pmin=1, pmax=4, mach=(0.05, 0.5)):
+    """Independent Navier-Stokes cases on the periodic box [0, 2pi]^3: cube
+    meshes n^3 with n ~ U{nmin..nmax}, degree p ~ U{pmin..pmax}, Mach
+    ~ U[mach]; case i's Fourier phases use seed + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        p = int(rng.integers(pmin, pmax + 1))
+        m = float(rng.uniform(*mach))
+        out.append(dict(n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(2 * math.pi,) * 3, p=p, mach=m, seed=seed + i))
+    return out
+
+
+def serving_requests(count=2000, rate=200.0, seed=1812, nmin=2, nmax=20, degrees=(2, 3, 4)):
+    """Poisson arrival stream: arrival times (s), cube meshes n^3 with n =
+    round(exp U[ln nmin, ln nmax]) (elements log-uniform), p uniform over
+    `degrees`, FP64 or mixed precision with probability 1/2, Mach
+    ~ U[0.05, 0.5]; request i's Fourier phases use seed + i."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    out = []
+    for i in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        p = int(degrees[int(rng.integers(0, len(degrees)))])
+        mixed = bool(rng.integers(0, 2))
+        m = float(rng.uniform(0.05, 0.5))
+        out.append(dict(t=float(t[i]), n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(2 * math.pi,) * 3, p=p, mixed=mixed,
+                        mach=m, seed=seed + i))
+    return out
 
 
 # ---- modal arrays for parity tests ---------------------------------------------

@@ -1,0 +1,177 @@
+"""Batched cases through the C ABI (dg_batch_*): one persistent launch over a
+work list of (case, element tile) items for cases of different meshes and
+degrees must give, case by case, exactly the single-context results (the same
+per-element arithmetic; the FD step of each case summed in the single-context
+order), for every tile shape; graph replays equal eager launches; the batched
+BDF2 step equals each case's own step; small cases are checked against the
+oracle."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1812_04789_amd import binding, inputs                      # noqa: E402
+from oracle import mesh as omesh, dg as odg, linear as olin, timestep as ots  # noqa: E402
+
+L = 2 * math.pi
+GAS = dict(gamma=1.4, mu=0.02, Pr=0.71, eta=7.0)
+MIX = [((2, 2, 2), 4), ((3, 2, 2), 1), ((2, 3, 2), 3), ((2, 2, 3), 2), ((3, 3, 2), 1), ((1, 2, 2), 3), ((2, 2, 2), 2)]
+
+
+def _cases(spec, gas=GAS):
+    return [dict(n=n, lo=(0, 0, 0), hi=(L, L, L), p=p, **gas) for n, p in spec]
+
+
+def _rand(batch, seed):
+    return torch.cat([torch.tensor(inputs.random_state(int(np.prod(c["n"])), c["p"], seed=seed + i).reshape(-1),
+                                   device="cuda") for i, c in enumerate(batch.cases)])
+
+
+def _randv(batch, seed):
+    return torch.cat([torch.tensor(inputs.random_vector(int(np.prod(c["n"])), c["p"], seed=seed + i).reshape(-1),
+                                   device="cuda") for i, c in enumerate(batch.cases)])
+
+
+def _singles(batch):
+    return [binding.Context(c["n"], c["lo"], c["hi"], c["p"], **{k: c[k] for k in GAS}) for c in batch.cases]
+
+
+def test_batched_operator_equals_single_cases():
+    print("batch operator", MIX, flush=True)
+    b = binding.Batch(_cases(MIX))
+    W, v = _rand(b, 100), _randv(b, 200)
+    a = 17.0
+    R = b.residual(W)
+    yf = b.jvp(W, R, v, a)
+    ye = b.jvp_exact(W, v, a)
+    torch.cuda.synchronize()
+    for c, ctx in enumerate(_singles(b)):
+        Wc, vc = b.split(W)[c].clone(), b.split(v)[c].clone()
+        Rc = ctx.residual(Wc)
+        assert torch.equal(b.split(R)[c], Rc), c
+        assert torch.equal(b.split(yf)[c], ctx.jvp(Wc, Rc, vc, a)), c
+        assert torch.equal(b.split(ye)[c], ctx.jvp_exact(Wc, vc, a)), c
+        ctx.close()
+    b.close()
+
+
+def test_batched_operator_matches_oracle():
+    spec = [((2, 1, 2), 1), ((1, 2, 2), 2), ((2, 2, 1), 3)]
+    b = binding.Batch(_cases(spec))
+    W, v = _rand(b, 300), _randv(b, 400)
+    R = b.residual(W)
+    ye = b.jvp_exact(W, v, 9.0)
+    torch.cuda.synchronize()
+    for c, (n, p) in enumerate(spec):
+        D = odg.Discretization(omesh.BoxMesh(n, (0, 0, 0), (L, L, L)), p, **GAS)
+        shape = (int(np.prod(n)), 5, (p + 1) ** 3)
+        Wc = b.split(W)[c].cpu().numpy().reshape(shape)
+        vc = b.split(v)[c].cpu().numpy().reshape(shape)
+        Ro = D.residual(Wc)
+        assert np.linalg.norm(b.split(R)[c].cpu().numpy().reshape(shape) - Ro) / np.linalg.norm(Ro) < 1e-12
+        yo = olin.jvp_exact(D, Wc, vc, 9.0)
+        assert np.linalg.norm(b.split(ye)[c].cpu().numpy().reshape(shape) - yo) / np.linalg.norm(yo) < 1e-12
+    b.close()
+
+
+@pytest.mark.parametrize("kind", ["residual", "jvp_fd", "jvp_exact"])
+def test_every_tile_shape_gives_the_same_result(kind):
+    b = binding.Batch(_cases(MIX))
+    W, v = _rand(b, 500), _randv(b, 600)
+    R = b.residual(W)
+    b.use_graphs(False)
+
+    def run():
+        if kind == "residual":
+            return b.residual(W)
+        if kind == "jvp_fd":
+            return b.jvp(W, R, v, 5.0)
+        return b.jvp_exact(W, v, 5.0)
+
+    ref = run().clone()
+    for threads in (128, 192, 256):
+        for cap in (32 * 1024, 160 * 1024):
+            for g in (1, 8):
+                b.set_tile(kind, threads, cap, g)
+                t = b.tile(kind)
+                assert t["threads"] == threads and t["lds_bytes"] <= 160 * 1024
+                assert torch.equal(run(), ref), (threads, cap, g)
+    tuned = b.tune(kind, W, R, v, reps=2)
+    assert tuned["candidates"] >= 4 and tuned["ms"] > 0
+    assert torch.equal(run(), ref)
+    b.close()
+
+
+def test_fd_graph_replays_match_eager():
+    b = binding.Batch(_cases(MIX))
+    W, v = _rand(b, 700), _randv(b, 800)
+    R = b.residual(W)
+    b.use_graphs(False)
+    ref = b.jvp(W, R, v, 3.0).clone()
+    b.use_graphs(True)
+    y = b.empty()
+    for it in range(4):
+        b.jvp(W, R, v, 3.0, y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), it
+        W.mul_(1.0)                       # eager work between replays
+        torch.cuda.synchronize()
+    v2 = v * 0.5                          # new operand: a new capture
+    y2 = b.jvp(W, R, v2, 3.0)
+    b.use_graphs(False)
+    assert torch.equal(y2, b.jvp(W, R, v2, 3.0))
+    b.close()
+
+
+def test_batch_rejects_mixed_physics():
+    cs = _cases([((2, 2, 2), 1)]) + _cases([((2, 2, 2), 2)], gas=dict(GAS, mu=0.0))
+    with pytest.raises(binding.DGError):
+        binding.Batch(cs)
+
+
+def _fourier_ic(ctx, case):
+    ks, ph = inputs.fourier_phases(case["seed"])
+    xq = ctx.quad_points().cpu().numpy()
+    return ctx.project(torch.tensor(inputs.fourier_state(xq, ks, ph, mach=case["mach"]).reshape(-1),
+                                    device="cuda"))
+
+
+def _levels(p):
+    return [4, 2, 1] if p == 4 else ([3, 2, 1] if p == 3 else ([2, 1] if p == 2 else [1]))
+
+
+def test_batched_bdf2_step_equals_single_steps_and_oracle():
+    """Four Fourier-IC cases of different size and degree, mixed-precision
+    pMG-FGMRES: each case's W^{n+1} from the batched step is bitwise its own
+    single-context step; the smallest case matches the FP64 oracle step."""
+    cases = [dict(n=(2, 2, 2), p=1, mach=0.3, seed=11), dict(n=(3, 3, 3), p=2, mach=0.2, seed=12),
+             dict(n=(2, 2, 3), p=3, mach=0.4, seed=13), dict(n=(2, 2, 2), p=4, mach=0.1, seed=14)]
+    gas = dict(gamma=1.4, mu=1.0 / 1600, Pr=0.71, eta=7.0)
+    b = binding.Batch([dict(c, lo=(0, 0, 0), hi=(L, L, L), **gas) for c in cases])
+    W0 = torch.cat([_fourier_ic(b.case(i), c) for i, c in enumerate(cases)])
+    popts = [binding.pmg_opts(_levels(c["p"]), prec_fine=binding.DG_FP32, prec_coarse=binding.DG_BF16,
+                              coarse_matrix_free=0) for c in cases]
+    fopts = binding.fgmres_opts(restart=40, rtol=1e-8)
+    W1, stats, st = b.bdf2_step(W0, None, 0.05, popts, fopts, workers=3)
+    assert st == binding.DG_OK
+    for i, c in enumerate(cases):
+        print("case", i, c, "newton", stats[i].newton, "its", stats[i].linear_iters, flush=True)
+        assert stats[i].max_rel_res_true <= 1e-8
+        ctx = binding.Context(c["n"], (0, 0, 0), (L, L, L), c["p"], **gas)
+        W1c, _ = ctx.bdf2_step(b.split(W0)[i].clone(), None, 0.05, popts[i], fopts)
+        assert torch.equal(b.split(W1)[i], W1c), i
+        ctx.close()
+    # oracle: the p = 1 case, FP64 step with block-Jacobi (the converged W^{n+1} is unique)
+    c = cases[0]
+    D = odg.Discretization(omesh.BoxMesh(c["n"], (0, 0, 0), (L, L, L)), c["p"], **gas)
+    ks, ph = inputs.fourier_phases(c["seed"])
+    Wo = D.project(inputs.fourier_state(D.quad_points(), ks, ph, mach=c["mach"]))
+    assert np.linalg.norm(b.split(W0)[0].cpu().numpy().reshape(Wo.shape) - Wo) / np.linalg.norm(Wo) < 1e-13
+    W1o, _ = ots.bdf2_step(D, Wo, None, 0.05, precond="bj", restart=40, rtol=1e-11)
+    got = b.split(W1)[0].cpu().numpy().reshape(Wo.shape)
+    assert np.linalg.norm(got - W1o) / np.linalg.norm(W1o) < 1e-10
+    b.close()
