@@ -162,6 +162,17 @@ def run(args):
                      linear_iters=[s_.linear_iters for s_ in st32], newton=[s_.newton for s_ in st32],
                      max_rel_res_true=max(s_.max_rel_res_true for s_ in st32))
 
+    # ---- batching (96 independent cases) and serving (Poisson request stream) ----------
+    batch = None
+    if not args.no_batch and args.workload == "tgv_p3_16":
+        batch = batch_bench(args)
+    serving = None
+    if not args.no_serving and args.workload == "tgv_p3_16" and args.serve_count > 0:
+        from paper_1812_04789_amd import serve
+        serving = serve.run(count=args.serve_count, rate=200.0, seed=1812, slots=args.serve_slots)
+        # the same stream offered below saturation: latency without queueing
+        serving["below_saturation"] = serve.run(count=40, rate=4.0, seed=1813, slots=args.serve_slots)
+
     # ---- CPU baseline: the oracle on a bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tgv_p3_16":
@@ -188,9 +199,81 @@ def run(args):
         "kernel_timing_note": "kernel families timed with HIP events on the library stream over one "
                               "instrumented FP64 step (eager launches); value is from the un-instrumented steps",
         "cpu_baseline": cpu,
+        "batch": batch,
+        "serving": serving,
     }
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def batch_bench(args):
+    """The 96-case batch: one persistent launch of the FD / exact product over
+    every case (default and autotuned tiles) against one launch per case, and
+    one mixed-precision BDF2 step of every case."""
+    import numpy as np
+    import torch
+    from paper_1812_04789_amd import binding, inputs, serve
+    wl = inputs.batch_cases()
+    gas = serve.GAS
+    b = binding.Batch([dict(c, **gas) for c in wl])
+    W0 = []
+    for i, c in enumerate(wl):
+        ctx = b.case(i)
+        ks, ph = inputs.fourier_phases(c["seed"])
+        W0.append(ctx.project(inputs.fourier_state_torch(ctx.quad_points(), ks, ph, gamma=gas["gamma"],
+                                                         mach=c["mach"]).reshape(-1)))
+    W0 = torch.cat(W0)
+    v = torch.tensor(np.random.default_rng(7).standard_normal(b.ndof), device="cuda")
+    R = b.residual(W0)
+    y = b.empty()
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"cases": len(wl), "total_dof": b.ndof, "elements": int(sum(np.prod(c["n"]) for c in wl)),
+           "degrees": {str(p): sum(1 for c in wl if c["p"] == p) for p in (1, 2, 3, 4)}}
+    reps = args.jvp_reps
+    jv = {}
+    for kind, fn in (("jvp_fd", lambda: b.jvp(W0, R, v, 30.0, y)), ("jvp_exact", lambda: b.jvp_exact(W0, v, 30.0, y))):
+        ms_default = timed(fn, reps)
+        tile_default = b.tile(kind)
+        tuned = b.tune(kind, W0, R, v, reps=3)
+        ms_tuned = timed(fn, reps)
+        jv[kind] = {"ms_default_tile": ms_default, "default_tile": tile_default, "ms_tuned": ms_tuned,
+                    "tuned_tile": tuned, "gdof_s": b.ndof / (ms_tuned * 1e-3) / 1e9}
+    # the same products as one launch per case (plain contexts on the same stream)
+    singles = [binding.Context(c["n"], c["lo"], c["hi"], c["p"], **gas) for c in wl]
+    Ws, Rs, vs, ys = b.split(W0), b.split(R), b.split(v), b.split(y)
+    ms_sep = timed(lambda: [ctx.jvp(Ws[i], Rs[i], vs[i], 30.0, ys[i]) for i, ctx in enumerate(singles)], 5)
+    for ctx in singles:
+        ctx.close()
+    jv["jvp_fd"]["ms_one_launch_per_case"] = ms_sep
+    jv["jvp_fd"]["batching_speedup"] = ms_sep / jv["jvp_fd"]["ms_tuned"]
+    out["jvp"] = jv
+    # one BDF2 step of every case, mixed precision, cases concurrent on 8 worker streams
+    popts = [serve.solver_opts(c["p"], True)[0] for c in wl]
+    fopts = binding.fgmres_opts(restart=40, rtol=1e-8)
+    b.bdf2_step(W0, None, 0.05, popts, fopts, workers=8, raise_on_noconv=False)   # warm-up (allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W1, st, status = b.bdf2_step(W0, None, 0.05, popts, fopts, workers=8, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["bdf2_step"] = {"seconds": el, "gdof_s": b.ndof / el / 1e9, "workers": 8, "status": status,
+                        "max_rel_res_true": max(x.max_rel_res_true for x in st),
+                        "newton_max": max(x.newton for x in st),
+                        "linear_iters_mean": float(np.mean([x.linear_iters for x in st])),
+                        "precision": "FP32 fine factors, BF16 assembled coarsest level"}
+    b.close()
+    return out
 
 
 def kernel_name(family, p, popts):
@@ -268,6 +351,10 @@ def main():
     ap.add_argument("--jvp-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=400)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--coarse", type=int, default=2, choices=[0, 1, 2],

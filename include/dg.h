@@ -309,6 +309,86 @@ dg_status dg_batch_bdf2_step(dg_batch* b, const double* Wn, const double* Wnm1, 
                              const fgmres_opts* fopts, double newton_rtol, int max_newton, int workers, double* Wnp1,
                              dg_step_stats* stats);
 
+/* ---- Device memory ------------------------------------------------------------
+ * dg_device_bytes: device memory the context holds now.
+ * dg_footprint_bytes: what a context of this mesh and degree allocates for one
+ * BDF2 step with these options (create, pmg_setup, FGMRES Krylov basis,
+ * Newton vectors, graph staging): factors, coarse operators and Krylov bases
+ * dominate.  Host-only arithmetic, no GPU needed; -1 on bad arguments. */
+double dg_device_bytes(const dg_ctx* ctx);
+double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_opts* popts, const fgmres_opts* fopts);
+
+/* ---- Serving loop -----------------------------------------------------------------
+ * Requests are implicit time steps (one dg_bdf2_step each) on straight periodic
+ * boxes.  `slots` worker threads each run one request at a time on the
+ * request's own stream, so up to `slots` requests overlap on the GPU.
+ * Admission is first-in first-out: the oldest waiting request starts when a
+ * slot is free and its footprint (dg_footprint_bytes) fits in hbm_budget next
+ * to the contexts the server holds (idle cached contexts are freed, least
+ * recently used first, to make room); a request that can never fit completes
+ * with DG_ENOMEM.  With cache = 1 a finished request's context stays resident
+ * and serves later requests of the same mesh, degree, gas and solver options.  Results do not
+ * depend on what else runs: each request's arithmetic is that of dg_bdf2_step
+ * on its own context.  Wn, Wnm1 (may be NULL) and Wnp1 are caller-owned
+ * device vectors: the inputs must be written (their producing work complete)
+ * before dg_server_submit, since the step runs on a stream of its own, and all
+ * three must stay valid until the request's response is polled; Wnp1 is
+ * complete when its response is returned.  Times are seconds on the server's
+ * clock (dg_server_time). */
+typedef struct dg_server dg_server;
+
+typedef struct {
+    int slots;              /* concurrent requests, 1..64                         */
+    double hbm_budget;      /* bytes of contexts the server may hold (0: 85% of
+                               the free device memory at creation)              */
+    int cache;              /* keep idle contexts for reuse (1) or free them (0) */
+} dg_server_opts;
+
+typedef struct {
+    dg_mesh_desc mesh;      /* vtx must be NULL                                   */
+    dg_phys phys;
+    int p;
+    double dt;
+    pmg_opts popts;
+    fgmres_opts fopts;
+    double newton_rtol;
+    int max_newton;
+    const double* Wn;
+    const double* Wnm1;
+    double* Wnp1;
+    long long tag;          /* returned in the response                           */
+} dg_request;
+
+typedef struct {
+    long long tag;
+    int status;             /* dg_status of the step                              */
+    int concurrent;         /* requests running when this one was admitted       */
+    double t_submit, t_admit, t_done;
+    double footprint;       /* bytes charged at admission                         */
+    double device_bytes;    /* bytes the context held after the step             */
+    size_t ndof;
+    dg_step_stats stats;
+} dg_response;
+
+typedef struct {
+    long long submitted, completed, pending;
+    int running, contexts;
+    double held_bytes, peak_held_bytes, budget_bytes;
+} dg_server_info;
+
+dg_status dg_server_create(const dg_server_opts* opts, dg_server** out);
+dg_status dg_server_destroy(dg_server* sv);   /* finishes queued requests first  */
+const char* dg_server_last_error(const dg_server* sv);
+double dg_server_time(const dg_server* sv);
+/* Queue one request (copied); returns at once. */
+dg_status dg_server_submit(dg_server* sv, const dg_request* rq);
+/* Move up to max finished responses to out (oldest first), waiting up to
+ * wait_ms for one if none is ready; returns the count (-1 on bad arguments). */
+int dg_server_poll(dg_server* sv, dg_response* out, int max, int wait_ms);
+/* Wait until every submitted request has finished. */
+dg_status dg_server_drain(dg_server* sv);
+dg_status dg_server_stats(dg_server* sv, dg_server_info* info);
+
 #ifdef __cplusplus
 }
 #endif

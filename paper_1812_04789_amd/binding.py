@@ -61,6 +61,30 @@ class BatchTile(ctypes.Structure):
                 ("items", ctypes.c_int)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("hbm_budget", ctypes.c_double), ("cache", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh", MeshDesc), ("phys", Phys), ("p", ctypes.c_int), ("dt", ctypes.c_double),
+                ("popts", PmgOpts), ("fopts", FgmresOpts), ("newton_rtol", ctypes.c_double),
+                ("max_newton", ctypes.c_int), ("Wn", ctypes.c_void_p), ("Wnm1", ctypes.c_void_p),
+                ("Wnp1", ctypes.c_void_p), ("tag", ctypes.c_longlong)]
+
+
+class Response(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_longlong), ("status", ctypes.c_int), ("concurrent", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("footprint", ctypes.c_double), ("device_bytes", ctypes.c_double), ("ndof", ctypes.c_size_t),
+                ("stats", StepStats)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("pending", ctypes.c_longlong),
+                ("running", ctypes.c_int), ("contexts", ctypes.c_int), ("held_bytes", ctypes.c_double),
+                ("peak_held_bytes", ctypes.c_double), ("budget_bytes", ctypes.c_double)]
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -103,8 +127,33 @@ SIGNATURES = {
     "dg_batch_tune": (_I, [_P, _I, _P, _P, _P, _I, ctypes.POINTER(BatchTile)]),
     "dg_batch_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _I,
                                 _P, ctypes.POINTER(StepStats)]),
+    "dg_device_bytes": (_D, [_P]),
+    "dg_footprint_bytes": (_D, [ctypes.POINTER(MeshDesc), _I, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts)]),
+    "dg_server_create": (_I, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
+    "dg_server_destroy": (_I, [_P]),
+    "dg_server_last_error": (ctypes.c_char_p, [_P]),
+    "dg_server_time": (_D, [_P]),
+    "dg_server_submit": (_I, [_P, ctypes.POINTER(Request)]),
+    "dg_server_poll": (_I, [_P, ctypes.POINTER(Response), _I, _I]),
+    "dg_server_drain": (_I, [_P]),
+    "dg_server_stats": (_I, [_P, ctypes.POINTER(ServerInfo)]),
 }
 KIND = {name: i for i, name in enumerate(KERNEL_KINDS)}
+
+
+def mesh_desc(n, lo, hi):
+    md = MeshDesc()
+    md.nx, md.ny, md.nz = (int(x) for x in n)
+    for d in range(3):
+        md.lo[d] = float(lo[d])
+        md.hi[d] = float(hi[d])
+    return md
+
+
+def footprint_bytes(n, lo, hi, p, popts, fopts):
+    """Device bytes a context of this mesh/degree allocates for one BDF2 step (host arithmetic only)."""
+    return float(load().dg_footprint_bytes(ctypes.byref(mesh_desc(n, lo, hi)), int(p), ctypes.byref(popts),
+                                           ctypes.byref(fopts)))
 
 _lib = None
 
@@ -298,6 +347,9 @@ class Context:
     def use_graphs(self, enable):
         self._check(self.lib.dg_use_graphs(self.h, 1 if enable else 0))
 
+    def device_bytes(self):
+        return float(self.lib.dg_device_bytes(self.h))
+
     def timing(self, enable):
         self._check(self.lib.dg_timing(self.h, 1 if enable else 0))
 
@@ -471,3 +523,79 @@ class Batch:
                                         st)
         self._check(s, (DG_OK,) if raise_on_noconv else (DG_OK, DG_ENOCONV))
         return Wnp1, list(st), s
+
+
+class Server:
+    """Serving loop (dg_server_*): submit BDF2 step requests, poll responses.
+
+    Inputs must be complete on the device before submit (the step runs on a
+    stream of its own); keep the tensors alive until the response is polled."""
+
+    def __init__(self, slots=4, hbm_budget=0.0, cache=True):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible")
+        o = ServerOpts(int(slots), float(hbm_budget), 1 if cache else 0)
+        h = ctypes.c_void_p()
+        st = self.lib.dg_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != DG_OK:
+            raise DGError(st, "dg_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_server_destroy(self.h)
+            self.h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def time(self):
+        return float(self.lib.dg_server_time(self.h))
+
+    def submit(self, tag, n, lo, hi, p, Wn, Wnp1, dt, popts, fopts, gamma=1.4, mu=0.0, Pr=0.72, eta=7.0,
+               Wnm1=None, newton_rtol=1e-10, max_newton=5):
+        rq = Request()
+        rq.mesh = mesh_desc(n, lo, hi)
+        rq.phys = Phys(gamma, mu, Pr, eta)
+        rq.p, rq.dt, rq.popts, rq.fopts = int(p), float(dt), popts, fopts
+        rq.newton_rtol, rq.max_newton = float(newton_rtol), int(max_newton)
+        rq.Wn, rq.Wnp1 = Wn.data_ptr(), Wnp1.data_ptr()
+        rq.Wnm1 = Wnm1.data_ptr() if Wnm1 is not None else None
+        rq.tag = int(tag)
+        st = self.lib.dg_server_submit(self.h, ctypes.byref(rq))
+        if st != DG_OK:
+            raise DGError(st, "dg_server_submit failed")
+        self._keep[int(tag)] = (Wn, Wnp1, Wnm1)
+
+    def poll(self, max_n=256, wait_ms=0):
+        buf = (Response * max_n)()
+        k = self.lib.dg_server_poll(self.h, buf, int(max_n), int(wait_ms))
+        if k < 0:
+            raise DGError(DG_EINVAL, "dg_server_poll failed")
+        out = [buf[i] for i in range(k)]
+        for r in out:
+            self._keep.pop(int(r.tag), None)
+        return out
+
+    def drain(self):
+        st = self.lib.dg_server_drain(self.h)
+        if st != DG_OK:
+            raise DGError(st, "dg_server_drain failed")
+
+    def info(self):
+        i = ServerInfo()
+        self.lib.dg_server_stats(self.h, ctypes.byref(i))
+        return dict(submitted=i.submitted, completed=i.completed, pending=i.pending, running=i.running,
+                    contexts=i.contexts, held_bytes=i.held_bytes, peak_held_bytes=i.peak_held_bytes,
+                    budget_bytes=i.budget_bytes)
+
+    def last_error(self):
+        return self.lib.dg_server_last_error(self.h).decode()

@@ -7,6 +7,7 @@
 // iteration to test convergence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -669,6 +670,76 @@ void no_alias(dg_ctx* ctx, const void* out, const void* in, const char* what) {
 }  // namespace
 
 // ============================================================================ C ABI
+
+// ---- device memory of a context ------------------------------------------------------------
+namespace {
+template <class T>
+double bytes_of(const DBuf<T>& b) { return (double)b.n * sizeof(T); }
+double krylov_bytes(const Krylov& K) {
+    return bytes_of(K.V) + bytes_of(K.Z) + bytes_of(K.H) + bytes_of(K.cs) + bytes_of(K.sn) + bytes_of(K.g) +
+           bytes_of(K.y) + bytes_of(K.h2) + bytes_of(K.sc);
+}
+}  // namespace
+
+extern "C" double dg_device_bytes(const dg_ctx* ctx) {
+    if (!ctx) return 0.0;
+    double b = bytes_of(ctx->vtx) + bytes_of(ctx->partial) + bytes_of(ctx->scal) + bytes_of(ctx->flag) +
+               bytes_of(ctx->tmp1) + bytes_of(ctx->tmp2) + bytes_of(ctx->tmp3) + bytes_of(ctx->W0) +
+               bytes_of(ctx->RW0) + bytes_of(ctx->blk) + bytes_of(ctx->otmp) + bytes_of(ctx->dtmp) +
+               bytes_of(ctx->nbrtr) + bytes_of(ctx->RW) + bytes_of(ctx->Ru) + bytes_of(ctx->xN) +
+               bytes_of(ctx->gin) + bytes_of(ctx->gout) + krylov_bytes(ctx->kc) + krylov_bytes(ctx->kf);
+    for (const Level& L : ctx->lv)
+        b += bytes_of(L.f64) + bytes_of(L.f32) + bytes_of(L.piv) + bytes_of(L.pos) + bytes_of(L.inv64) +
+             bytes_of(L.inv32) + bytes_of(L.x) + bytes_of(L.b) + bytes_of(L.r) + bytes_of(L.t) + bytes_of(L.z) +
+             bytes_of(L.od64) + bytes_of(L.oo64) + bytes_of(L.od32) + bytes_of(L.oo32) + bytes_of(L.od16) +
+             bytes_of(L.oo16);
+    return b;
+}
+
+// What a context of this mesh and degree allocates for one BDF2 step with
+// these options (the allocations of dg_create, pmg_setup, fgmres_step and
+// dg_bdf2_step, with graphs on): the admission size of the serving loop.
+extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_opts* po, const fgmres_opts* fo) {
+    if (!mesh || !po || !fo || p < 1 || p > MAXP || po->n_levels < 1 || po->n_levels > 4) return -1.0;
+    const double ne = (double)mesh->nx * mesh->ny * mesh->nz;
+    const double nv = (p + 1.0) * (p + 1) * (p + 1), nb = 5 * nv, N = ne * nb;
+    // Krylov workspace of restart m on n entries (basis V, directions Z, Hessenberg and rotations)
+    auto krylov = [](double m, double n) { return (2 * m + 1) * n * 8 + ((m + 1) * m + 5 * m + 2 + 8) * 8; };
+    double b = 24 * ne * 8 + (double)RED_BLOCKS * 256 * 8 + S_COUNT * 8 + 4 * 4 + 3 * N * 8;   // create
+    b += 2 * N * 8 + ne * nb * nb * 8 + (double)nbr_trace_size(p, (int)ne) * 8;  // W0, RW0, blocks, traces
+    double tmp = 0.0;
+    for (int l = 0; l < po->n_levels; ++l) {
+        const int pl = po->p_level[l];
+        const double nbl = 5.0 * (pl + 1) * (pl + 1) * (pl + 1), ndl = ne * nbl, sz = ne * nbl * nbl;
+        const bool use32 = (l == 0) ? (po->prec_fine == DG_FP32) : (po->prec_coarse != DG_FP64);
+        const bool assembled = l > 0 && (po->coarse_matrix_free == 0 ||
+                                         (po->coarse_matrix_free == 2 && l == po->n_levels - 1));
+        b += 2 * ndl * 4 + 5 * ndl * 8;                                           // pivots, positions, vectors
+        if (assembled) {
+            tmp = std::max(tmp, 7 * sz * 8);
+            b += 7 * sz * (po->prec_coarse == DG_FP64 ? 8 : (po->prec_coarse == DG_FP32 ? 4 : 2));
+        }
+        if (use32) b += sz * 4;
+        else if (l > 0) b += sz * 8;
+        if (nbl <= (use32 ? INV_MAX_N : 135)) b += sz * (use32 ? 4 : 8);
+        if (l == po->n_levels - 1 && po->n_levels > 1)
+            b += krylov(po->coarsest_iters, ndl);                                 // coarsest GMRES
+    }
+    b += tmp;
+    if (po->prec_fine == DG_FP64) {        // level-0 factors took the block buffer: FP32 inverses need a workspace
+        double ws = 0.0;
+        for (int l = 1; l < po->n_levels; ++l) {
+            const int pl = po->p_level[l];
+            const double nbl = 5.0 * (pl + 1) * (pl + 1) * (pl + 1);
+            if (po->prec_coarse != DG_FP64 && nbl <= INV_MAX_N) ws = std::max(ws, ne * nbl * nbl * 8);
+        }
+        b += ws;
+    }
+    b += krylov(fo->restart, N);                                                   // FGMRES
+    b += 3 * N * 8 + 2 * N * 8;                                                    // Newton, graph staging
+    return b;
+}
+
 extern "C" {
 
 dg_status dg_create(const dg_mesh_desc* mesh, const dg_phys* phys, int p, void* hip_stream, dg_ctx** out) {

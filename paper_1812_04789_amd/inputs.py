@@ -136,6 +136,41 @@ def fourier_state(x, ks, phases, gamma=1.4, mach=0.3, amp=0.1):
     return conserved(rho, fourier_velocity(x, ks, phases, amp), p, gamma)
 
 
+def fourier_state_torch(xq, ks, phases, gamma=1.4, mach=0.3, amp=0.1, L=2 * math.pi, chunk=1 << 18):
+    """fourier_state evaluated with torch on the device of `xq` (points (..., 3),
+    float64): the same separable sum as _fourier_raw and the same RMS scale
+    (computed on the host), for preparing many large inputs quickly."""
+    import torch
+    g = (np.arange(16) + 0.5) * L / 16
+    G = np.stack(np.meshgrid(g, g, g, indexing='ij'), axis=-1).reshape(-1, 3)
+    rms = math.sqrt(float(np.mean(np.sum(_fourier_raw(G, ks, phases, L) ** 2, axis=-1))))
+    scale = amp / rms
+    ki = ks.astype(int)
+    kmax = int(np.abs(ki).max())
+    m = 2 * kmax + 1
+    dev = xq.device
+    ax = torch.arange(-kmax, kmax + 1, device=dev, dtype=torch.float64)
+    Cs = []
+    for c in range(3):
+        C = np.zeros((m, m, m), complex)
+        C[ki[:, 0] + kmax, ki[:, 1] + kmax, ki[:, 2] + kmax] = np.exp(1j * phases[:, c])
+        Cs.append(torch.tensor(C.reshape(m * m, m).T.copy(), device=dev))
+    y = xq.reshape(-1, 3).to(torch.float64) * (2 * math.pi / L)
+    vel = torch.empty(y.shape[0], 3, dtype=torch.float64, device=dev)
+    for a in range(0, y.shape[0], chunk):
+        yy = y[a:a + chunk]
+        E = [torch.exp(1j * yy[:, d:d + 1] * ax) for d in range(3)]
+        for c in range(3):
+            t = (E[2] @ Cs[c]).reshape(-1, m, m)
+            t = (t * E[1][:, None, :]).sum(-1)
+            vel[a:a + chunk, c] = (t * E[0]).sum(-1).real * scale
+    rho = torch.ones(y.shape[0], dtype=torch.float64, device=dev)
+    p = torch.full_like(rho, 1.0 / (gamma * mach * mach))
+    En = p / (gamma - 1.0) + 0.5 * rho * (vel * vel).sum(-1)
+    out = torch.cat([rho[:, None], rho[:, None] * vel, En[:, None]], dim=1)
+    return out.reshape(tuple(xq.shape[:-1]) + (5,))
+
+
 # ---- batch and serving workloads ------------------------------------------------
 def batch_cases(count=96, seed=1812, nmin=4, nmax=12, pmin=1, pmax=4, mach=(0.05, 0.5)):
     """Independent Navier-Stokes cases on the periodic box [0, 2pi]^3: cube

@@ -140,6 +140,11 @@ def _fourier_ic(ctx, case):
                                     device="cuda"))
 
 
+def _fourier_ic_dev(ctx, case):
+    ks, ph = inputs.fourier_phases(case["seed"])
+    return ctx.project(inputs.fourier_state_torch(ctx.quad_points(), ks, ph, mach=case["mach"]).reshape(-1))
+
+
 def _levels(p):
     return [4, 2, 1] if p == 4 else ([3, 2, 1] if p == 3 else ([2, 1] if p == 2 else [1]))
 
@@ -174,4 +179,32 @@ def test_batched_bdf2_step_equals_single_steps_and_oracle():
     W1o, _ = ots.bdf2_step(D, Wo, None, 0.05, precond="bj", restart=40, rtol=1e-11)
     got = b.split(W1)[0].cpu().numpy().reshape(Wo.shape)
     assert np.linalg.norm(got - W1o) / np.linalg.norm(W1o) < 1e-10
+    b.close()
+
+
+def test_full_batch_workload_sampled():
+    """The 96-case workload (cube meshes 4^3..12^3, p = 1..4, Fourier ICs) in
+    the launch configuration the benchmark times (tuned tiles): sampled cases
+    of the batched FD and exact products equal their single-context products."""
+    wl = inputs.batch_cases()
+    gas = dict(gamma=1.4, mu=1.0 / 1600, Pr=0.71, eta=7.0)
+    b = binding.Batch([dict(c, **gas) for c in wl])
+    W0 = torch.cat([_fourier_ic_dev(b.case(i), c) for i, c in enumerate(wl)])
+    v = torch.tensor(np.random.default_rng(4).standard_normal(b.ndof), device="cuda")
+    R = b.residual(W0)
+    tf = b.tune("jvp_fd", W0, R, v, reps=2)
+    te = b.tune("jvp_exact", W0, R, v, reps=2)
+    print("tiles", tf, te, flush=True)
+    yf = b.jvp(W0, R, v, 30.0)
+    ye = b.jvp_exact(W0, v, 30.0)
+    torch.cuda.synchronize()
+    for c in (0, 17, 41, 63, 95) + tuple(i for i, x in enumerate(wl) if x["p"] == 4)[:2]:
+        x = wl[c]
+        ctx = binding.Context(x["n"], x["lo"], x["hi"], x["p"], **gas)
+        Wc, vc = b.split(W0)[c].clone(), b.split(v)[c].clone()
+        Rc = ctx.residual(Wc)
+        assert torch.equal(b.split(R)[c], Rc), c
+        assert torch.equal(b.split(yf)[c], ctx.jvp(Wc, Rc, vc, 30.0)), c
+        assert torch.equal(b.split(ye)[c], ctx.jvp_exact(Wc, vc, 30.0)), c
+        ctx.close()
     b.close()

@@ -42,3 +42,13 @@ def test_serving_requests_draws():
     assert all(2 <= r["n"][0] <= 20 for r in rq)
     assert {r["p"] for r in rq} == {2, 3, 4}
     assert 0.35 < np.mean([r["mixed"] for r in rq]) < 0.65
+
+
+def test_fourier_state_torch_equals_numpy():
+    torch = __import__("torch")
+    ks, ph = inputs.fourier_phases(9)
+    x = np.random.default_rng(3).uniform(0.0, 2 * math.pi, size=(7, 11, 3))
+    a = inputs.fourier_state(x, ks, ph, mach=0.2)
+    b = inputs.fourier_state_torch(torch.tensor(x), ks, ph, mach=0.2, chunk=13).numpy()
+    assert b.shape == a.shape
+    assert np.abs(a - b).max() < 1e-9 * np.abs(a).max()
