@@ -94,10 +94,10 @@ struct Level {
     // assembled inherited operator: diagonal + 6 face blocks per element
     bool assembled = false;
     int op_prec = DG_FP64;
-    DBuf<double> od64, oo64;
-    DBuf<float> od32, oo32;
-    DBuf<unsigned short> od16, oo16;
-    void release() { inv64.release(); inv32.release(); od64.release(); oo64.release(); od32.release(); oo32.release(); od16.release(); oo16.release();
+    DBuf<double> op64;               // packed rows (launch_bsr_pack layout)
+    DBuf<float> op32;
+    DBuf<unsigned short> op16;
+    void release() { inv64.release(); inv32.release(); op64.release(); op32.release(); op16.release();
                      f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
 };
 
@@ -243,9 +243,9 @@ void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
     if (L.assembled) {
         const double nbc = L.nb, sz = L.op_prec == DG_FP64 ? 8.0 : (L.op_prec == DG_FP32 ? 4.0 : 2.0);
         timed(ctx, DG_K_BSR, ctx->ne * (7.0 * nbc * nbc * sz + 16.0 * nbc), ctx->ne * 14.0 * nbc * nbc, [&] {
-            if (L.op_prec == DG_FP64) return launch_bsr7<double>(ctx->a, L.od64.p, L.oo64.p, x, y, L.nb, ctx->s);
-            if (L.op_prec == DG_FP32) return launch_bsr7<float>(ctx->a, L.od32.p, L.oo32.p, x, y, L.nb, ctx->s);
-            return launch_bsr7<unsigned short>(ctx->a, L.od16.p, L.oo16.p, x, y, L.nb, ctx->s);
+            if (L.op_prec == DG_FP64) return launch_bsr7<double>(ctx->a, L.op64.p, x, y, L.nb, ctx->s);
+            if (L.op_prec == DG_FP32) return launch_bsr7<float>(ctx->a, L.op32.p, x, y, L.nb, ctx->s);
+            return launch_bsr7<unsigned short>(ctx->a, L.op16.p, x, y, L.nb, ctx->s);
         });
         return;
     }
@@ -431,21 +431,16 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
             ctx->otmp.ensure(6 * sz);
             CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
             CK(launch_offdiag_blocks(ctx->a, ctx->W0.p, L.p, ctx->otmp.p, ctx->s));
+            const size_t pk = bsr_entries(ctx->ne, L.nb);
             if (L.op_prec == DG_FP64) {
-                L.od64.ensure(sz);
-                L.oo64.ensure(6 * sz);
-                CK(launch_copy(sz, ctx->dtmp.p, L.od64.p, ctx->s));
-                CK(launch_copy(6 * sz, ctx->otmp.p, L.oo64.p, ctx->s));
+                L.op64.ensure(pk);
+                CK(launch_bsr_pack<double>(ctx->dtmp.p, ctx->otmp.p, L.op64.p, ctx->ne, L.nb, ctx->s));
             } else if (L.op_prec == DG_FP32) {
-                L.od32.ensure(sz);
-                L.oo32.ensure(6 * sz);
-                CK(launch_convert_fp64_to_fp32(ctx->dtmp.p, L.od32.p, sz, ctx->s));
-                CK(launch_convert_fp64_to_fp32(ctx->otmp.p, L.oo32.p, 6 * sz, ctx->s));
+                L.op32.ensure(pk);
+                CK(launch_bsr_pack<float>(ctx->dtmp.p, ctx->otmp.p, L.op32.p, ctx->ne, L.nb, ctx->s));
             } else {
-                L.od16.ensure(sz);
-                L.oo16.ensure(6 * sz);
-                CK(launch_convert_fp64_to_bf16(ctx->dtmp.p, L.od16.p, sz, ctx->s));
-                CK(launch_convert_fp64_to_bf16(ctx->otmp.p, L.oo16.p, 6 * sz, ctx->s));
+                L.op16.ensure(pk);
+                CK(launch_bsr_pack<unsigned short>(ctx->dtmp.p, ctx->otmp.p, L.op16.p, ctx->ne, L.nb, ctx->s));
             }
         }
         if (L.use32) {
@@ -468,13 +463,12 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         std::swap(ctx->lv[0].f64.p, ctx->blk.p);
         std::swap(ctx->lv[0].f64.n, ctx->blk.n);
     }
-    // explicit inverses for the smoother apply: FP32 blocks up to INV_MAX_N
-    // and every block up to 135.  The inverse costs about as much as the PLU
-    // itself; for large FP64 blocks the blocked triangular solves are cheaper
-    // over the ~100 applies of one time step.
+    // explicit inverses for the smoother apply: blocks up to 135 entries.  For
+    // larger blocks the inverse costs more than the PLU itself and the blocked
+    // triangular solves are cheaper over the ~100 applies of one time step.
     for (int l = 0; l < o->n_levels; ++l) {
         Level& L = ctx->lv[l];
-        L.inv = L.nb <= (L.use32 ? INV_MAX_N : 135);
+        L.inv = L.nb <= INV_POLICY_N;
         if (!L.inv) continue;
         const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
         const double fl = ctx->ne * 2.0 * (double)L.nb * L.nb * L.nb;
@@ -691,8 +685,7 @@ extern "C" double dg_device_bytes(const dg_ctx* ctx) {
     for (const Level& L : ctx->lv)
         b += bytes_of(L.f64) + bytes_of(L.f32) + bytes_of(L.piv) + bytes_of(L.pos) + bytes_of(L.inv64) +
              bytes_of(L.inv32) + bytes_of(L.x) + bytes_of(L.b) + bytes_of(L.r) + bytes_of(L.t) + bytes_of(L.z) +
-             bytes_of(L.od64) + bytes_of(L.oo64) + bytes_of(L.od32) + bytes_of(L.oo32) + bytes_of(L.od16) +
-             bytes_of(L.oo16);
+             bytes_of(L.op64) + bytes_of(L.op32) + bytes_of(L.op16);
     return b;
 }
 
@@ -717,11 +710,12 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         b += 2 * ndl * 4 + 5 * ndl * 8;                                           // pivots, positions, vectors
         if (assembled) {
             tmp = std::max(tmp, 7 * sz * 8);
-            b += 7 * sz * (po->prec_coarse == DG_FP64 ? 8 : (po->prec_coarse == DG_FP32 ? 4 : 2));
+            b += (double)bsr_entries((int)ne, (int)nbl) *
+                 (po->prec_coarse == DG_FP64 ? 8 : (po->prec_coarse == DG_FP32 ? 4 : 2));
         }
         if (use32) b += sz * 4;
         else if (l > 0) b += sz * 8;
-        if (nbl <= (use32 ? INV_MAX_N : 135)) b += sz * (use32 ? 4 : 8);
+        if (nbl <= INV_POLICY_N) b += sz * (use32 ? 4 : 8);
         if (l == po->n_levels - 1 && po->n_levels > 1)
             b += krylov(po->coarsest_iters, ndl);                                 // coarsest GMRES
     }
@@ -731,7 +725,7 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         for (int l = 1; l < po->n_levels; ++l) {
             const int pl = po->p_level[l];
             const double nbl = 5.0 * (pl + 1) * (pl + 1) * (pl + 1);
-            if (po->prec_coarse != DG_FP64 && nbl <= INV_MAX_N) ws = std::max(ws, ne * nbl * nbl * 8);
+            if (po->prec_coarse != DG_FP64 && nbl <= INV_POLICY_N) ws = std::max(ws, ne * nbl * nbl * 8);
         }
         b += ws;
     }

@@ -1173,55 +1173,136 @@ hipError_t launch_offdiag_blocks(const DGArgs& a, const double* W, int pc, doubl
     }
 }
 
-// y_e = D_e x_e + sum_f O_{e,f} x_nb(e,f) on a coarse level: 7 blocks per
-// element row (column-major, storage SF: double, float or bf16 bits),
-// accumulation in AT (double for FP64/FP32 storage, float for BF16).
-__device__ __forceinline__ float bf16_to_f(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
+// ---- assembled coarse operator: sliced row-major block-sparse product ----------------------
+// y_e = D_e x_e + sum_f O_{e,f} x_nb(e,f), 7 blocks per element row.  Storage:
+// global row g = e nbc + r holds the row r of the 7 blocks of element e, each
+// padded to ldr = roundup(nbc, 8) entries (zeros); rows are grouped by 64 (one
+// wavefront) and within a group stored chunk-major: chunk k (16 bytes of the
+// row) of the 64 rows is contiguous, so each 16-byte load of a wavefront is
+// one contiguous 1 KB read.  Entries are FP64, FP32 or BF16 (RNE); products
+// accumulate in FP64 (FP64/FP32 storage) or FP32 (BF16 storage).  The x
+// blocks an element's rows need are staged in LDS once per workgroup.
+__device__ __forceinline__ unsigned short bf16_rne(double v) {
+    const unsigned int b = __float_as_uint((float)v);
+    return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
 template <class SF>
-__device__ __forceinline__ double ld_coef(const SF* p, size_t i) { return (double)p[i]; }
+__device__ __forceinline__ SF to_storage(double v) { return (SF)v; }
 template <>
-__device__ __forceinline__ double ld_coef<unsigned short>(const unsigned short* p, size_t i) { return bf16_to_f(p[i]); }
+__device__ __forceinline__ unsigned short to_storage<unsigned short>(double v) { return bf16_rne(v); }
+
+template <class SF>
+__global__ void __launch_bounds__(256) bsr_pack_kernel(int ne, int nbc, const double* __restrict__ diag,
+                                                       const double* __restrict__ off, SF* __restrict__ out) {
+    constexpr int W = 16 / sizeof(SF);
+    const int ldr = bsr_ldr(nbc);
+    const size_t nrows = (size_t)ne * nbc;
+    const size_t total = bsr_entries(ne, nbc);
+    const int nk = 7 * ldr / W;                     // 16-byte chunks per row
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int j = (int)(i % W);
+        const size_t t = i / W;
+        const int lane = (int)(t % 64);
+        const size_t t2 = t / 64;
+        const int kc = (int)(t2 % nk);
+        const size_t grp = t2 / nk;
+        const size_t g = grp * 64 + lane;
+        double v = 0.0;
+        if (g < nrows) {
+            const size_t e = g / nbc;
+            const int r = (int)(g % nbc);
+            const int k = kc * W + j, f = k / ldr, c = k % ldr;
+            if (c < nbc)
+                v = (f == 0) ? diag[(e * nbc + c) * nbc + r] : off[((e * 6 + (f - 1)) * nbc + c) * nbc + r];
+        }
+        out[i] = to_storage<SF>(v);
+    }
+}
 
 template <class SF, class AT>
-__global__ void __launch_bounds__(64) bsr7_kernel(MeshDev m, int nbc, const SF* __restrict__ diag,
-                                                  const SF* __restrict__ off, const double* __restrict__ x,
-                                                  double* __restrict__ y) {
-    extern __shared__ double xs[];       // 7 * nbc
-    const int e = blockIdx.x, t = threadIdx.x;
-    for (int i = t; i < nbc; i += 64) xs[i] = x[(size_t)e * nbc + i];
-    for (int f = 0; f < 6; ++f) {
-        const int nb = nbr_of(m, e, f);
-        for (int i = t; i < nbc; i += 64) xs[(1 + f) * nbc + i] = x[(size_t)nb * nbc + i];
-    }
-    __syncthreads();
-    const SF* db = diag + (size_t)e * nbc * nbc;
-    const SF* obk = off + (size_t)e * 6 * nbc * nbc;
-    for (int r = t; r < nbc; r += 64) {
-        AT acc = 0;
-        for (int c = 0; c < nbc; ++c) acc += (AT)ld_coef(db, (size_t)c * nbc + r) * (AT)xs[c];
-        for (int f = 0; f < 6; ++f) {
-            const SF* ofb = obk + (size_t)f * nbc * nbc;
-            const double* xf = xs + (1 + f) * nbc;
-            for (int c = 0; c < nbc; ++c) acc += (AT)ld_coef(ofb, (size_t)c * nbc + r) * (AT)xf[c];
-        }
-        y[(size_t)e * nbc + r] = (double)acc;
+__device__ __forceinline__ void bsr_chunk(const SF* p, const AT* xv, AT& acc);
+template <>
+__device__ __forceinline__ void bsr_chunk<double, double>(const double* p, const double* xv, double& acc) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    acc = fma(a.x, xv[0], acc);
+    acc = fma(a.y, xv[1], acc);
+}
+template <>
+__device__ __forceinline__ void bsr_chunk<float, double>(const float* p, const double* xv, double& acc) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    acc = fma((double)a.x, xv[0], acc);
+    acc = fma((double)a.y, xv[1], acc);
+    acc = fma((double)a.z, xv[2], acc);
+    acc = fma((double)a.w, xv[3], acc);
+}
+template <>
+__device__ __forceinline__ void bsr_chunk<unsigned short, float>(const unsigned short* p, const float* xv,
+                                                                  float& acc) {
+    const uint4 a = *reinterpret_cast<const uint4*>(p);
+    const unsigned int w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc = fmaf(__uint_as_float(w[q] << 16), xv[2 * q], acc);
+        acc = fmaf(__uint_as_float(w[q] & 0xFFFF0000u), xv[2 * q + 1], acc);
     }
 }
 
+template <class SF, class AT>
+__global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const SF* __restrict__ A,
+                                                       const double* __restrict__ x, double* __restrict__ y) {
+    extern __shared__ double smraw[];
+    AT* xs = reinterpret_cast<AT*>(smraw);          // [element in range][7][ldr]
+    constexpr int W = 16 / sizeof(SF);
+    const int ldr = bsr_ldr(nbc);
+    const size_t nrows = (size_t)m.ne * nbc;
+    const size_t g0 = (size_t)blockIdx.x * blockDim.x;
+    const size_t glast = min(g0 + blockDim.x, nrows) - 1;
+    const int e_first = (int)(g0 / nbc);
+    const int nel = (int)(glast / nbc) - e_first + 1;
+    for (int i = threadIdx.x; i < nel * 7 * ldr; i += blockDim.x) {
+        const int c = i % ldr, t = i / ldr, f = t % 7, le = t / 7;
+        const int e = e_first + le;
+        const int src = (f == 0) ? e : nbr_of(m, e, f - 1);
+        xs[i] = (c < nbc) ? (AT)x[(size_t)src * nbc + c] : (AT)0;
+    }
+    __syncthreads();
+    const size_t g = g0 + threadIdx.x;
+    if (g >= nrows) return;
+    const int e = (int)(g / nbc);
+    const AT* xe = xs + (size_t)(e - e_first) * 7 * ldr;
+    const int nk = 7 * ldr / W;
+    const SF* base = A + ((g / 64) * (size_t)nk * 64 + (g % 64)) * W;
+    AT acc = 0;
+    for (int kc = 0; kc < nk; ++kc) bsr_chunk<SF, AT>(base + (size_t)kc * 64 * W, xe + kc * W, acc);
+    y[g] = (double)acc;
+}
+
 template <class SF>
-hipError_t launch_bsr7(const DGArgs& a, const SF* diag, const SF* off, const double* x, double* y, int nbc,
-                       hipStream_t s) {
-    using AT = typename std::conditional<std::is_same<SF, unsigned short>::value, float, double>::type;
-    hipLaunchKernelGGL((bsr7_kernel<SF, AT>), dim3(a.m.ne), dim3(64), 7 * nbc * sizeof(double), s, a.m, nbc, diag, off,
-                       x, y);
+hipError_t launch_bsr_pack(const double* diag, const double* off, SF* out, int ne, int nbc, hipStream_t s) {
+    const size_t total = bsr_entries(ne, nbc);
+    const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(bsr_pack_kernel<SF>, dim3(grid), dim3(256), 0, s, ne, nbc, diag, off, out);
     return hipGetLastError();
 }
-template hipError_t launch_bsr7<double>(const DGArgs&, const double*, const double*, const double*, double*, int,
-                                        hipStream_t);
-template hipError_t launch_bsr7<float>(const DGArgs&, const float*, const float*, const double*, double*, int,
-                                       hipStream_t);
-template hipError_t launch_bsr7<unsigned short>(const DGArgs&, const unsigned short*, const unsigned short*,
-                                                const double*, double*, int, hipStream_t);
+
+template <class SF>
+hipError_t launch_bsr7(const DGArgs& a, const SF* A, const double* x, double* y, int nbc, hipStream_t s) {
+    using AT = typename std::conditional<std::is_same<SF, unsigned short>::value, float, double>::type;
+    const size_t nrows = (size_t)a.m.ne * nbc;
+    const unsigned grid = (unsigned)((nrows + 255) / 256);
+    const size_t lds = (size_t)(256 / nbc + 2) * 7 * bsr_ldr(nbc) * sizeof(AT);
+    hipLaunchKernelGGL((bsr_rows_kernel<SF, AT>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y);
+    return hipGetLastError();
+}
+template hipError_t launch_bsr_pack<double>(const double*, const double*, double*, int, int, hipStream_t);
+template hipError_t launch_bsr_pack<float>(const double*, const double*, float*, int, int, hipStream_t);
+template hipError_t launch_bsr_pack<unsigned short>(const double*, const double*, unsigned short*, int, int,
+                                                    hipStream_t);
+template hipError_t launch_bsr7<double>(const DGArgs&, const double*, const double*, double*, int, hipStream_t);
+template hipError_t launch_bsr7<float>(const DGArgs&, const float*, const double*, double*, int, hipStream_t);
+template hipError_t launch_bsr7<unsigned short>(const DGArgs&, const unsigned short*, const double*, double*, int,
+                                                hipStream_t);
 
 // ---- element diagonal blocks (Sec. 6.3) ------------------------------------------------------
 // Column j = (beta, mode) of K_e = a M_e + dR_e/dW_e is the forward-mode

@@ -159,13 +159,23 @@ hipError_t launch_lu_inverse(const TF* LU, const int* pos, double* Xw, TF* Xout,
 template <class TF>
 hipError_t launch_inv_gemv(const TF* X, const double* r, double* z, int nblk, int n, hipStream_t s);
 constexpr int INV_MAX_N = 320;
+constexpr int INV_POLICY_N = 135;     // the smoother applies an explicit inverse up to this block size
 // Extract coarse principal sub-blocks (FP64 column-major fine blocks) and round to TF.
 template <class TF>
 hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);
-// Block-sparse product y = K x with 7 blocks per element row (diagonal + 6 faces)
+// Block-sparse product y = K x with 7 blocks per element row (diagonal + 6
+// faces), stored sliced row-major: rows padded to bsr_ldr(nbc) entries per
+// block, grouped by 64 rows, 16-byte chunks of a group contiguous.
+__host__ __device__ inline int bsr_ldr(int nbc) { return (nbc + 7) & ~7; }
+__host__ __device__ inline size_t bsr_entries(int ne, int nbc) {
+    return ((size_t)ne * nbc + 63) / 64 * 64 * 7 * (size_t)bsr_ldr(nbc);
+}
+// Pack the column-major diagonal [e][c][r] and face blocks [e][f][c][r] (FP64)
+// into that layout, rounding to TF (BF16: round to nearest even).
 template <class TF>
-hipError_t launch_bsr7(const DGArgs& a, const TF* diag, const TF* off, const double* x, double* y, int nbc,
-                       hipStream_t s);
+hipError_t launch_bsr_pack(const double* diag, const double* off, TF* out, int ne, int nbc, hipStream_t s);
+template <class TF>
+hipError_t launch_bsr7(const DGArgs& a, const TF* A, const double* x, double* y, int nbc, hipStream_t s);
 hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s);
 hipError_t launch_convert_fp64_to_bf16(const double* x, unsigned short* y, size_t n, hipStream_t s);
 

@@ -335,22 +335,31 @@ __global__ void __launch_bounds__(SOLVE_THREADS)
         const int kb = min(TS, n - k0);
         {
             // lane i holds row i of the diagonal triangle (loads issued together)
-            double lrow[TS];
+            TF lrow[TS];
+            const int li = (lane < kb) ? lane : 0;
+#pragma unroll
+            for (int j = 0; j < TS; ++j) lrow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li];
 #pragma unroll
             for (int j = 0; j < TS; ++j)
-                lrow[j] = (j < kb && lane < kb && lane > j) ? (double)a[(size_t)(k0 + j) * n + k0 + lane] : 0.0;
+                if (!(j < kb && lane < kb && lane > j)) lrow[j] = TF(0);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = 0; j < TS - 1; ++j) {
                 const double xj = __shfl(xi, j, 64);
-                xi -= lrow[j] * xj;
+                xi -= (double)lrow[j] * xj;
             }
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
         for (int row = k0 + kb + t; row < n; row += SOLVE_THREADS) {
+            // the panel's factor entries of this row, all loads in flight at once
+            TF av[TS];
+#pragma unroll
+            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
             double acc = x[row];
-            for (int j = 0; j < kb; ++j) acc -= (double)a[(size_t)(k0 + j) * n + row] * x[k0 + j];
+#pragma unroll
+            for (int j = 0; j < TS; ++j)
+                if (j < kb) acc -= (double)av[j] * x[k0 + j];
             x[row] = acc;
         }
         __syncthreads();
@@ -360,25 +369,33 @@ __global__ void __launch_bounds__(SOLVE_THREADS)
     for (int k0 = nb0; k0 >= 0; k0 -= TS) {
         const int kb = min(TS, n - k0);
         {
-            double urow[TS];
+            TF urow[TS];
+            const int ui = (lane < kb) ? lane : 0;
+#pragma unroll
+            for (int j = 0; j < TS; ++j) urow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui];
 #pragma unroll
             for (int j = 0; j < TS; ++j)
-                urow[j] = (j < kb && lane < kb && lane <= j) ? (double)a[(size_t)(k0 + j) * n + k0 + lane] : 0.0;
+                if (!(j < kb && lane < kb && lane <= j)) urow[j] = TF(0);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = TS - 1; j >= 0; --j) {
                 if (j < kb) {
-                    if (lane == j) xi /= urow[j];
+                    if (lane == j) xi /= (double)urow[j];
                     const double xj = __shfl(xi, j, 64);
-                    if (lane < j) xi -= urow[j] * xj;
+                    if (lane < j) xi -= (double)urow[j] * xj;
                 }
             }
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
         for (int row = t; row < k0; row += SOLVE_THREADS) {
+            TF av[TS];
+#pragma unroll
+            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
             double acc = x[row];
-            for (int j = 0; j < kb; ++j) acc -= (double)a[(size_t)(k0 + j) * n + row] * x[k0 + j];
+#pragma unroll
+            for (int j = 0; j < TS; ++j)
+                if (j < kb) acc -= (double)av[j] * x[k0 + j];
             x[row] = acc;
         }
         __syncthreads();
