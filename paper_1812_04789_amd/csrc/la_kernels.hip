@@ -12,18 +12,46 @@ namespace dg {
 
 namespace {
 constexpr int KCH = 8;    // dot products per pass of the multi-dot
+constexpr int GS_MAXK = 64;   // largest Krylov basis handled by the Arnoldi / back-solve kernels
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;       // the butterfly leaves the same sum in every lane
+}
+
+// Block sum (blockDim.x a multiple of 64): butterfly inside each wavefront,
+// then the wavefront partials in wavefront order.  Every thread gets the sum.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (t < s) sh[t] += sh[t + s];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    double r = 0.0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
     __syncthreads();
     return r;
+}
+
+// Block sums of kn <= K accumulators at once (one barrier pair for all):
+// thread c < kn writes the sum of acc[c] to out[c * ostride].
+template <int K>
+__device__ __forceinline__ void block_sum_cols(const double (&acc)[K], int kn, double* sh, double* out,
+                                               size_t ostride) {
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+        if (c < kn) {
+            const double v = wave_sum(acc[c]);
+            if ((threadIdx.x & 63) == 0) sh[w * K + c] = v;
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < kn) {
+        double r = 0.0;
+        for (int i = 0; i < nw; ++i) r += sh[i * K + threadIdx.x];
+        out[threadIdx.x * ostride] = r;
+    }
+    __syncthreads();
 }
 }  // namespace
 
@@ -41,13 +69,7 @@ __global__ void __launch_bounds__(RED_THREADS)
         for (int c = 0; c < KCH; ++c)
             if (c < kn) acc[c] = fma(X[(size_t)(k0 + c) * ldx + i], yi, acc[c]);
     }
-#pragma unroll
-    for (int c = 0; c < KCH; ++c) {
-        if (c < kn) {
-            const double s = block_sum(acc[c], sh);
-            if (threadIdx.x == 0) partial[(size_t)(k0 + c) * gridDim.x + blockIdx.x] = s;
-        }
-    }
+    block_sum_cols<KCH>(acc, kn, sh, partial + (size_t)k0 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) sum_stage2(const double* __restrict__ partial, int nparts,
@@ -249,16 +271,29 @@ __global__ void givens_kernel(double* H, int ldh, int j, double* cs, double* sn,
 }
 // y = R^-1 g[0:k] for the k x k upper triangle of H.  After a breakdown
 // (zero new direction) the trailing columns are exactly zero: they are dropped.
-__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
-    int ke = k;
-    for (int i = 0; i < k; ++i)
-        if (!(fabs(H[(size_t)i * ldh + i]) > 0.0)) { ke = i; break; }
-    for (int i = ke; i < k; ++i) y[i] = 0.0;
-    for (int i = ke - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int c = i + 1; c < ke; ++c) s -= H[(size_t)c * ldh + i] * y[c];
-        y[i] = s / H[(size_t)i * ldh + i];
+__global__ void __launch_bounds__(256) backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
+    // the k x k triangle and g staged in LDS by all threads, then one thread solves
+    __shared__ double sH[GS_MAXK * GS_MAXK];
+    __shared__ double sg[GS_MAXK], sy[GS_MAXK];
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+        const int c = t / k, i = t % k;
+        sH[c * GS_MAXK + i] = H[(size_t)c * ldh + i];
     }
+    for (int t = threadIdx.x; t < k; t += blockDim.x) sg[t] = g[t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ke = k;
+        for (int i = 0; i < k; ++i)
+            if (!(fabs(sH[i * GS_MAXK + i]) > 0.0)) { ke = i; break; }
+        for (int i = ke; i < k; ++i) sy[i] = 0.0;
+        for (int i = ke - 1; i >= 0; --i) {
+            double s = sg[i];
+            for (int c = i + 1; c < ke; ++c) s -= sH[c * GS_MAXK + i] * sy[c];
+            sy[i] = s / sH[i * GS_MAXK + i];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k; t += blockDim.x) y[t] = sy[t];
 }
 // Combine the two Gram-Schmidt passes: h[i] += h2[i] (i <= j), set h[j+1] = sqrt(nrm2) and
 // the inverse norm for normalisation.
@@ -278,7 +313,8 @@ hipError_t launch_givens(double* H, int ldh, int j, double* cs, double* sn, doub
     return hipGetLastError();
 }
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(1), 0, s, H, ldh, k, g, y);
+    if (k < 1 || k > GS_MAXK) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, s, H, ldh, k, g, y);
     return hipGetLastError();
 }
 hipError_t launch_gs_finish(double* hcol, const double* h2, int jp1, const double* nrm2, double* nrm, hipStream_t s) {
@@ -300,7 +336,6 @@ hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s)
 //   K6  (one block) h += h2, H[j+1,j] = ||w||, Givens rotation j, |g_{j+1}|
 //   K7  w     /= ||w||
 // Every sum has a fixed order: the result depends only on the data.
-constexpr int GS_MAXK = 64;
 constexpr int GS_CH = 16;
 
 __global__ void __launch_bounds__(RED_THREADS)
@@ -318,12 +353,7 @@ __global__ void __launch_bounds__(RED_THREADS)
             for (int c = 0; c < GS_CH; ++c)
                 if (c0 + c < k) acc[c] = fma(V[(size_t)(c0 + c) * n + i], wi, acc[c]);
         }
-#pragma unroll
-        for (int c = 0; c < GS_CH; ++c)
-            if (c0 + c < k) {
-                const double sm = block_sum(acc[c], sh);
-                if (threadIdx.x == 0) part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = sm;
-            }
+        block_sum_cols<GS_CH>(acc, min(GS_CH, k - c0), sh, part + (size_t)c0 * gridDim.x + blockIdx.x, gridDim.x);
     }
 }
 
@@ -364,12 +394,7 @@ __global__ void __launch_bounds__(RED_THREADS)
             for (int c = 0; c < GS_CH; ++c)
                 if (c0 + c < k) acc[c] = fma(V[(size_t)(c0 + c) * n + i], wi, acc[c]);
         }
-#pragma unroll
-        for (int c = 0; c < GS_CH; ++c)
-            if (c0 + c < k) {
-                const double sm = block_sum(acc[c], sh);
-                if (threadIdx.x == 0) part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = sm;
-            }
+        block_sum_cols<GS_CH>(acc, min(GS_CH, k - c0), sh, part + (size_t)c0 * gridDim.x + blockIdx.x, gridDim.x);
     }
 }
 
@@ -382,26 +407,35 @@ __global__ void __launch_bounds__(RED_THREADS)
     double acc = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
     const double nrm2 = block_sum(acc, sh);
-    if (threadIdx.x != 0) return;
+    // column j, the rotations and g_j staged in LDS, then one thread rotates
+    __shared__ double sh_h[GS_MAXK + 1], sh_c[GS_MAXK], sh_s[GS_MAXK];
     double* h = H + (size_t)j * ldh;
-    for (int i = 0; i <= j; ++i) h[i] += h2[i];
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        sh_h[i] = h[i] + h2[i];
+        sh_c[i] = cs[i];
+        sh_s[i] = sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const double nr = sqrt(nrm2);
-    h[j + 1] = nr;
+    sh_h[j + 1] = nr;
     nrm_out[0] = nr;
     for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-        h[i] = t;
+        const double t = sh_c[i] * sh_h[i] + sh_s[i] * sh_h[i + 1];
+        sh_h[i + 1] = -sh_s[i] * sh_h[i] + sh_c[i] * sh_h[i + 1];
+        sh_h[i] = t;
     }
-    const double a = h[j], b = h[j + 1];
+    const double a = sh_h[j], b = sh_h[j + 1];
     const double r = hypot(a, b);
     const double c = (r > 0.0) ? a / r : 1.0, sg = (r > 0.0) ? b / r : 0.0;
     cs[j] = c;
     sn[j] = sg;
-    h[j] = r;
-    h[j + 1] = 0.0;
-    g[j + 1] = -sg * g[j];
-    g[j] = c * g[j];
+    sh_h[j] = r;
+    sh_h[j + 1] = 0.0;
+    for (int i = 0; i <= j + 1; ++i) h[i] = sh_h[i];
+    const double gj = g[j];
+    g[j + 1] = -sg * gj;
+    g[j] = c * gj;
     est[0] = fabs(g[j + 1]);
 }
 
