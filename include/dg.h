@@ -92,7 +92,14 @@ typedef struct {
  *                 product); 1 = matrix-free for every coarse level (the
  *                 level-0 finite-difference product of Eq. DG-mf on the
  *                 zero-padded vector, then restricted); 2 = assembled on the
- *                 coarsest level only, matrix-free above it. */
+ *                 coarsest level only, matrix-free above it.
+ *  coarsest_plain 0 = when the coarsest level is assembled with blocks of at
+ *                 most 64 rows, its GMRES(BJ) runs on the right-preconditioned
+ *                 operator K D^-1 stored directly (face blocks K_{e,f} X_nb,
+ *                 unit diagonal; one block-sparse product per iteration, and
+ *                 x = D^-1 V y at the end: the same Krylov space and iterate up
+ *                 to rounding); 1 = a product with K and a block-Jacobi apply
+ *                 per iteration. */
 typedef struct {
     int n_levels;
     int p_level[4];
@@ -102,6 +109,7 @@ typedef struct {
     int prec_fine;
     int prec_coarse;
     int coarse_matrix_free;
+    int coarsest_plain;
 } pmg_opts;
 
 /* FGMRES(restart) (Sec. 6), restart 1..63: x0 = 0, converged when the recomputed true

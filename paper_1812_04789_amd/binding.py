@@ -32,7 +32,8 @@ class Phys(ctypes.Structure):
 class PmgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("p_level", ctypes.c_int * 4), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("coarsest_iters", ctypes.c_int),
-                ("prec_fine", ctypes.c_int), ("prec_coarse", ctypes.c_int), ("coarse_matrix_free", ctypes.c_int)]
+                ("prec_fine", ctypes.c_int), ("prec_coarse", ctypes.c_int), ("coarse_matrix_free", ctypes.c_int),
+                ("coarsest_plain", ctypes.c_int)]
 
 
 class FgmresOpts(ctypes.Structure):
@@ -180,13 +181,14 @@ class DGError(RuntimeError):
 
 
 def pmg_opts(levels, nu_pre=2, nu_post=2, omega=1.0, coarsest_iters=30, prec_fine=DG_FP64,
-             prec_coarse=DG_FP64, coarse_matrix_free=1):
+             prec_coarse=DG_FP64, coarse_matrix_free=1, coarsest_plain=0):
     o = PmgOpts()
     o.n_levels = len(levels)
     for i, p in enumerate(levels):
         o.p_level[i] = int(p)
     o.nu_pre, o.nu_post, o.omega, o.coarsest_iters = nu_pre, nu_post, omega, coarsest_iters
     o.prec_fine, o.prec_coarse, o.coarse_matrix_free = prec_fine, prec_coarse, coarse_matrix_free
+    o.coarsest_plain = coarsest_plain
     return o
 
 

@@ -22,9 +22,7 @@
 using namespace dg;
 
 namespace dg {
-hipError_t launch_givens(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est, hipStream_t s);
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s);
-hipError_t launch_gs_finish(double* hcol, const double* h2, int jp1, const double* nrm2, double* nrm, hipStream_t s);
 hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s);
 }  // namespace dg
 
@@ -88,6 +86,8 @@ struct Level {
     DBuf<int> piv, pos;
     bool use32 = false;
     bool inv = false;          // explicit inverse (nb <= INV_MAX_N) applied by GEMV
+    bool inv_done = false;     // inverse already formed during setup (folded level)
+    bool fold = false;         // coarsest assembled level stored as K D^-1 (unit diagonal, 6 face blocks)
     DBuf<double> inv64;
     DBuf<float> inv32;
     DBuf<double> x, b, r, t, z;
@@ -240,6 +240,7 @@ void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
         return;
     }
     const Level& L = ctx->lv[l];
+    if (L.assembled && L.fold) fail(ctx, DG_ESTATE, "folded coarsest operator used as a plain operator");
     if (L.assembled) {
         const double nbc = L.nb, sz = L.op_prec == DG_FP64 ? 8.0 : (L.op_prec == DG_FP32 ? 4.0 : 2.0);
         timed(ctx, DG_K_BSR, ctx->ne * (7.0 * nbc * nbc * sz + 16.0 * nbc), ctx->ne * 14.0 * nbc * nbc, [&] {
@@ -279,12 +280,63 @@ void arnoldi_orth(dg_ctx* ctx, Krylov& K, int j, size_t n) {
     });
 }
 
+// y = (K D^-1) x on the folded coarsest level: x plus the six face products.
+void folded_op(dg_ctx* ctx, int l, const double* x, double* y) {
+    const Level& L = ctx->lv[l];
+    const double nbc = L.nb, sz = L.op_prec == DG_FP64 ? 8.0 : (L.op_prec == DG_FP32 ? 4.0 : 2.0);
+    timed(ctx, DG_K_BSR, ctx->ne * (6.0 * nbc * nbc * sz + 16.0 * nbc), ctx->ne * 12.0 * nbc * nbc, [&] {
+        if (L.op_prec == DG_FP64) return launch_bsr_unit<double>(ctx->a, L.op64.p, x, y, L.nb, ctx->s);
+        if (L.op_prec == DG_FP32) return launch_bsr_unit<float>(ctx->a, L.op32.p, x, y, L.nb, ctx->s);
+        return launch_bsr_unit<unsigned short>(ctx->a, L.op16.p, x, y, L.nb, ctx->s);
+    });
+}
+
 // Coarsest SOLVE: right-preconditioned GMRES(BJ) from x = 0 for exactly
-// `iters` steps, all on the device (no host synchronisation).
+// `iters` steps, all on the device (no host synchronisation).  On a folded
+// level the Arnoldi process runs on K D^-1 directly (one product per step)
+// and x = D^-1 (V y) at the end: the same Krylov space and iterate.
 void coarse_gmres(dg_ctx* ctx, int l, const double* b, double* x, int iters) {
     Level& L = ctx->lv[l];
     Krylov& K = ctx->kc;
     const size_t n = L.ndof;
+    if (L.fold) {
+        dot(ctx, b, b, n, K.sc.p + 3);
+        CK(launch_init_g(K.g.p, iters + 1, K.sc.p + 3, ctx->s));
+        CK(launch_scale_dev(n, b, K.g.p, 1, K.V.p, ctx->s));
+        const bool fuse = bsr_grid(ctx->ne, L.nb) <= RED_BLOCKS;
+        const double nbc = L.nb, sz = L.op_prec == DG_FP64 ? 8.0 : (L.op_prec == DG_FP32 ? 4.0 : 2.0);
+        for (int j = 0; j < iters; ++j) {
+            const double* x = K.V.p + (size_t)j * n;
+            double* y = K.V.p + (size_t)(j + 1) * n;
+            if (!fuse) {
+                folded_op(ctx, l, x, y);
+                arnoldi_orth(ctx, K, j, n);
+                continue;
+            }
+            // product and first Gram-Schmidt pass in one launch (timed as the product)
+            int np = 0;
+            timed(ctx, DG_K_BSR, ctx->ne * (6.0 * nbc * nbc * sz + 16.0 * nbc) + 8.0 * (j + 1) * n,
+                  ctx->ne * 12.0 * nbc * nbc + 2.0 * (j + 1) * n, [&] {
+                if (L.op_prec == DG_FP64)
+                    return launch_bsr_unit_dots<double>(ctx->a, L.op64.p, x, y, L.nb, K.V.p, j + 1, ctx->partial.p,
+                                                        &np, ctx->s);
+                if (L.op_prec == DG_FP32)
+                    return launch_bsr_unit_dots<float>(ctx->a, L.op32.p, x, y, L.nb, K.V.p, j + 1, ctx->partial.p,
+                                                       &np, ctx->s);
+                return launch_bsr_unit_dots<unsigned short>(ctx->a, L.op16.p, x, y, L.nb, K.V.p, j + 1,
+                                                            ctx->partial.p, &np, ctx->s);
+            });
+            timed(ctx, DG_K_ARNOLDI, 24.0 * (j + 1) * (double)n, 6.0 * (j + 1) * (double)n, [&] {
+                return launch_arnoldi_cgs2_after_dots(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p,
+                                                      K.sc.p + 1, K.sc.p + 2, ctx->partial.p, np, ctx->s);
+            });
+        }
+        CK(launch_backsolve(K.H.p, K.m + 1, iters, K.g.p, K.y.p, ctx->s));
+        CK(launch_fill(n, 0.0, L.t.p, ctx->s));
+        CK(launch_multi_axpy(n, iters, K.y.p, 1, K.V.p, n, L.t.p, ctx->s));
+        bj_apply(ctx, l, L.t.p, x);
+        return;
+    }
     dot(ctx, b, b, n, K.sc.p + 3);
     CK(launch_init_g(K.g.p, iters + 1, K.sc.p + 3, ctx->s));
     CK(launch_scale_dev(n, b, K.g.p, 1, K.V.p, ctx->s));
@@ -380,10 +432,46 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
     if (o->prec_coarse != DG_FP64 && o->prec_coarse != DG_FP32 && o->prec_coarse != DG_BF16)
         fail(ctx, DG_EINVAL, "prec_coarse must be FP64, FP32 or BF16");
     if (o->coarse_matrix_free < 0 || o->coarse_matrix_free > 2) fail(ctx, DG_EINVAL, "coarse_matrix_free must be 0, 1 or 2");
+    if (o->coarsest_plain != 0 && o->coarsest_plain != 1) fail(ctx, DG_EINVAL, "coarsest_plain must be 0 or 1");
 }
 
 double lu_bytes(dg_ctx* ctx, int nb, double s) { return ctx->ne * 2.0 * s * (double)nb * nb; }
 double lu_flops(dg_ctx* ctx, int nb) { return ctx->ne * (2.0 / 3.0) * (double)nb * nb * nb; }
+
+// Pack the assembled operator of level L (diagonal in dtmp unless nblk = 6,
+// face blocks in otmp) at its storage precision.
+void pack_operator(dg_ctx* ctx, Level& L, int nblk) {
+    const size_t pk = bsr_entries(ctx->ne, L.nb, nblk);
+    if (L.op_prec == DG_FP64) {
+        L.op64.ensure(pk);
+        CK(launch_bsr_pack<double>(ctx->dtmp.p, ctx->otmp.p, L.op64.p, ctx->ne, L.nb, nblk, ctx->s));
+    } else if (L.op_prec == DG_FP32) {
+        L.op32.ensure(pk);
+        CK(launch_bsr_pack<float>(ctx->dtmp.p, ctx->otmp.p, L.op32.p, ctx->ne, L.nb, nblk, ctx->s));
+    } else {
+        L.op16.ensure(pk);
+        CK(launch_bsr_pack<unsigned short>(ctx->dtmp.p, ctx->otmp.p, L.op16.p, ctx->ne, L.nb, nblk, ctx->s));
+    }
+}
+
+// Explicit block inverses of level L from its PLU factors (ws: FP64
+// workspace of ne nb^2 entries, used for FP32 factors only).
+void form_inverse(dg_ctx* ctx, Level& L, double* ws) {
+    const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
+    const double fl = ctx->ne * 2.0 * (double)L.nb * L.nb * L.nb;
+    if (L.use32) {
+        L.inv32.ensure(sz);
+        timed(ctx, DG_K_LU, 4.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
+            return launch_lu_inverse<float>(L.f32.p, L.pos.p, ws, L.inv32.p, ctx->ne, L.nb, ctx->s);
+        });
+    } else {
+        L.inv64.ensure(sz);
+        timed(ctx, DG_K_LU, 8.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
+            return launch_lu_inverse<double>(L.f64.p, L.pos.p, L.inv64.p, (double*)nullptr, ctx->ne, L.nb, ctx->s);
+        });
+    }
+    L.inv_done = true;
+}
 
 void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* o) {
     check_pmg_opts(ctx, o);
@@ -413,6 +501,9 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         L.assembled = l > 0 && (o->coarse_matrix_free == 0 ||
                                 (o->coarse_matrix_free == 2 && l == o->n_levels - 1));
         L.op_prec = o->prec_coarse;
+        L.inv = L.nb <= INV_POLICY_N;
+        L.inv_done = false;
+        L.fold = L.assembled && l == o->n_levels - 1 && L.inv && L.nb <= FOLD_MAX_N && o->coarsest_plain == 0;
         L.piv.ensure((size_t)ctx->ne * L.nb);
         L.pos.ensure((size_t)ctx->ne * L.nb);
         L.x.ensure(L.ndof);
@@ -431,17 +522,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
             ctx->otmp.ensure(6 * sz);
             CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
             CK(launch_offdiag_blocks(ctx->a, ctx->W0.p, L.p, ctx->otmp.p, ctx->s));
-            const size_t pk = bsr_entries(ctx->ne, L.nb);
-            if (L.op_prec == DG_FP64) {
-                L.op64.ensure(pk);
-                CK(launch_bsr_pack<double>(ctx->dtmp.p, ctx->otmp.p, L.op64.p, ctx->ne, L.nb, ctx->s));
-            } else if (L.op_prec == DG_FP32) {
-                L.op32.ensure(pk);
-                CK(launch_bsr_pack<float>(ctx->dtmp.p, ctx->otmp.p, L.op32.p, ctx->ne, L.nb, ctx->s));
-            } else {
-                L.op16.ensure(pk);
-                CK(launch_bsr_pack<unsigned short>(ctx->dtmp.p, ctx->otmp.p, L.op16.p, ctx->ne, L.nb, ctx->s));
-            }
+            if (!L.fold) pack_operator(ctx, L, 7);
         }
         if (L.use32) {
             L.f32.ensure(sz);
@@ -457,6 +538,14 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
                 timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(L.f64.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
             }
         }
+        if (L.fold) {
+            // K D^-1: the block inverses first (FP64 workspace: the diagonal
+            // sub-blocks in dtmp are not needed once factored), then the fold
+            form_inverse(ctx, L, ctx->dtmp.p);
+            if (L.use32) CK(launch_fold_inverse<float>(ctx->a, L.nb, ctx->otmp.p, L.inv32.p, ctx->s));
+            else CK(launch_fold_inverse<double>(ctx->a, L.nb, ctx->otmp.p, L.inv64.p, ctx->s));
+            pack_operator(ctx, L, 6);
+        }
     }
     // level 0 FP64 factors live in blk (factored in place)
     if (!ctx->lv[0].use32) {
@@ -468,23 +557,9 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     // triangular solves are cheaper over the ~100 applies of one time step.
     for (int l = 0; l < o->n_levels; ++l) {
         Level& L = ctx->lv[l];
-        L.inv = L.nb <= INV_POLICY_N;
-        if (!L.inv) continue;
-        const size_t sz = (size_t)ctx->ne * L.nb * L.nb;
-        const double fl = ctx->ne * 2.0 * (double)L.nb * L.nb * L.nb;
-        if (L.use32) {
-            ctx->blk.ensure(sz);          // FP64 workspace (the FP64 blocks are no longer needed)
-            L.inv32.ensure(sz);
-            timed(ctx, DG_K_LU, 4.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
-                return launch_lu_inverse<float>(L.f32.p, L.pos.p, ctx->blk.p, L.inv32.p, ctx->ne, L.nb, ctx->s);
-            });
-        } else {
-            L.inv64.ensure(sz);
-            timed(ctx, DG_K_LU, 8.0 * sz + 8.0 * 2.0 * sz, fl, [&] {
-                return launch_lu_inverse<double>(L.f64.p, L.pos.p, L.inv64.p, (double*)nullptr, ctx->ne, L.nb,
-                                                 ctx->s);
-            });
-        }
+        if (!L.inv || L.inv_done) continue;
+        if (L.use32) ctx->blk.ensure((size_t)ctx->ne * L.nb * L.nb);   // FP64 workspace (the FP64 blocks are no longer needed)
+        form_inverse(ctx, L, ctx->blk.p);
     }
     if (o->n_levels > 1) {
         const Level& Lc = ctx->lv.back();
@@ -707,10 +782,12 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         const bool use32 = (l == 0) ? (po->prec_fine == DG_FP32) : (po->prec_coarse != DG_FP64);
         const bool assembled = l > 0 && (po->coarse_matrix_free == 0 ||
                                          (po->coarse_matrix_free == 2 && l == po->n_levels - 1));
+        const bool fold = assembled && l == po->n_levels - 1 && nbl <= INV_POLICY_N && nbl <= FOLD_MAX_N &&
+                          po->coarsest_plain == 0;
         b += 2 * ndl * 4 + 5 * ndl * 8;                                           // pivots, positions, vectors
         if (assembled) {
             tmp = std::max(tmp, 7 * sz * 8);
-            b += (double)bsr_entries((int)ne, (int)nbl) *
+            b += (double)bsr_entries((int)ne, (int)nbl, fold ? 6 : 7) *
                  (po->prec_coarse == DG_FP64 ? 8 : (po->prec_coarse == DG_FP32 ? 4 : 2));
         }
         if (use32) b += sz * 4;
@@ -725,7 +802,9 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         for (int l = 1; l < po->n_levels; ++l) {
             const int pl = po->p_level[l];
             const double nbl = 5.0 * (pl + 1) * (pl + 1) * (pl + 1);
-            if (po->prec_coarse != DG_FP64 && nbl <= INV_POLICY_N) ws = std::max(ws, ne * nbl * nbl * 8);
+            const bool fold = l == po->n_levels - 1 && nbl <= FOLD_MAX_N && po->coarsest_plain == 0 &&
+                              (po->coarse_matrix_free == 0 || po->coarse_matrix_free == 2);
+            if (po->prec_coarse != DG_FP64 && nbl <= INV_POLICY_N && !fold) ws = std::max(ws, ne * nbl * nbl * 8);
         }
         b += ws;
     }

@@ -21,6 +21,7 @@
 //    lambda_q = J_F,q sum_c l(z_c)^2 w_c / detJ(line through q, c);
 //  * curved (Q1) elements recompute the metric from the 8 vertices.
 #include "internal.h"
+#include "reduce.h"
 #include "physics.h"
 
 namespace dg {
@@ -88,14 +89,43 @@ __device__ __forceinline__ int nbr_of(const MeshDev& m, int e, int f) {
 template <int P>
 struct Sz {
     static constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NB = 5 * NQ;
-    static constexpr int R0 = (15 * NQ > 60 * NF) ? 15 * NQ : 60 * NF;   // interpolation buffers | collapse
-    static constexpr int OFF_U = R0;                                       // Gauss values (5 NQ)
-    static constexpr int OFF_G = OFF_U + 5 * NQ;                           // Gauss ref. gradients (15 NQ)
-    static constexpr int OFF_E = OFF_G + 15 * NQ;                          // tangential sweep (90 NF) | test-back
-    static constexpr int OFF_F = OFF_E + 90 * NF;                          // face integrands (120 NF)
-    static constexpr int TOT = OFF_F + 120 * NF;
 };
-
+// Face phase of the fused kernel (both process the faces in rounds of NQ face
+// points, N whole faces per round, and spread each round onto the Gauss lines):
+//  UP = true:  the neighbour data of all six faces is collapsed and swept up
+//              front; own traces from stored Gauss-point gradients.  Fewer,
+//              longer phases: faster where the registers allow two waves per
+//              SIMD (degree <= 3, real arithmetic).
+//  UP = false: each round collapses its own faces; own trace gradients from
+//              the face trace (collocation derivative on the face): 40 NQ of
+//              LDS, for degree 4 and the dual-number product.
+template <int P, int MODE>
+struct FaceMode { static constexpr bool UP = (MODE < M_TANGENT) && (P <= 3); };
+template <int P, bool UP>
+struct Lay;
+template <int P>
+struct Lay<P, true> {
+    static constexpr int NQ = Sz<P>::NQ, NF = Sz<P>::NF;
+    // [0, RA): interpolation buffers (15 NQ) | neighbour collapse of all faces (60 NF) |
+    //          face integrands of one round (20 NQ) | test A, B (20 NQ)
+    static constexpr int RA = (20 * NQ > 60 * NF) ? 20 * NQ : 60 * NF;
+    static constexpr int OFF_U = RA;                                       // Gauss values (5 NQ)
+    static constexpr int OFF_G = OFF_U + 5 * NQ;                           // Gauss ref. gradients (15 NQ)
+    static constexpr int OFF_E = OFF_G + 15 * NQ;                          // tangential sweep (90 NF) | test-back (15 NQ)
+    static constexpr int TOT = OFF_E + ((90 * NF > 15 * NQ) ? 90 * NF : 15 * NQ);
+};
+template <int P>
+struct Lay<P, false> {
+    static constexpr int NQ = Sz<P>::NQ;
+    // [0, 20 NQ): interpolation buffers (15 NQ) | one round: neighbour collapse (10 NQ)
+    //             + own traces (5 NQ), then face integrands (20 NQ) | test A, B (20 NQ)
+    static constexpr int OFF_U = 20 * NQ;                                  // Gauss values (5 NQ)
+    static constexpr int OFF_G = OFF_U;                                    // (no stored gradients)
+    static constexpr int OFF_E = OFF_U + 5 * NQ;                           // tangential sweep | test-back (15 NQ)
+    static constexpr int TOT = OFF_E + 15 * NQ;
+};
+template <int P, int MODE>
+using LayOf = Lay<P, FaceMode<P, MODE>::UP>;
 
 template <int P, bool DUAL>
 struct Launch;
@@ -161,47 +191,74 @@ __device__ __forceinline__ T load_state(const double* W, const double* v, double
 //   up, gxp: + trace and its reference gradient; um, gxm: - trace;
 //   nrm: unit normal out of +;  Jip/Jim: dxi/dx on each side;
 //   lam_p/lam_m: BR2 lifting factors;  sc = w_face * J_F.
+// BR2 penalty and symmetry terms of a face point, added to the normal flux Fn
+// (Roe + averaged viscous) to give the integrand fo[0..19] (see face_integrand):
+// G+- = -1/2 F_v(u+-, [u] (x) n+), penalty eta/2 (lam+ G+ + lam- G-).n, symmetry
+// -(dxi/dx) G+ on the reference gradients of the + test functions.
+template <class T>
+__device__ __forceinline__ void face_penalty_symmetry(const T up[5], const T um[5], const double nrm[3],
+                                                      const double Jip[3][3], double lam_p, double lam_m, double sc,
+                                                      const Gas& gas, const T Fn[5], T* fo) {
+    T jmp[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) jmp[a] = up[a] - um[a];
+    const double cp = 0.5 * gas.eta * lam_p, cm = 0.5 * gas.eta * lam_m;
+    T Fs[5];
+    {
+        T Gm[5][3];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Gm[a][j] = 0.0;
+        flux_v_rank1_acc(um, jmp, nrm, gas, -0.5, Gm);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) Fs[a] = Fn[a] + cm * (Gm[a][0] * nrm[0] + Gm[a][1] * nrm[1] + Gm[a][2] * nrm[2]);
+    }
+    T Gp[5][3];
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Gp[a][j] = 0.0;
+    flux_v_rank1_acc(up, jmp, nrm, gas, -0.5, Gp);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        fo[a] = sc * (Fs[a] + cp * (Gp[a][0] * nrm[0] + Gp[a][1] * nrm[1] + Gp[a][2] * nrm[2]));
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            fo[5 + a * 3 + k] = -sc * (Jip[k][0] * Gp[a][0] + Jip[k][1] * Gp[a][1] + Jip[k][2] * Gp[a][2]);
+    }
+}
+
 template <class T, bool NS>
 __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3], const T um[5], const T gxm[5][3],
                                                const double nrm[3], const double Jip[3][3], const double Jim[3][3],
                                                double lam_p, double lam_m, double sc, const Gas& gas, T* fo) {
-    T Fh[5];
-    roe_flux(up, um, nrm, gas.gamma, Fh);
+    T Fn[5];
+    roe_flux(up, um, nrm, gas.gamma, Fn);
     if constexpr (NS) {
-        T gp[5][3], gm[5][3], X[5][3];
+        // averaged viscous flux, normal component only: 1/2 (F_v(u+, g+) + F_v(u-, g-)).n
+        {
+            T g[5][3];
 #pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const T jmp = up[a] - um[a];
+            for (int a = 0; a < 5; ++a)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                gp[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
-                gm[a][j] = Jim[0][j] * gxm[a][0] + Jim[1][j] * gxm[a][1] + Jim[2][j] * gxm[a][2];
-                X[a][j] = jmp * nrm[j];
-            }
+                for (int j = 0; j < 3; ++j)
+                    g[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
+            flux_v_n_acc(up, g, gas, 0.5, nrm, Fn);
         }
-        T Fv[5][3], Gp[5][3], Gm[5][3];
+        {
+            T g[5][3];
 #pragma unroll
-        for (int a = 0; a < 5; ++a)
+            for (int a = 0; a < 5; ++a)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) Fv[a][j] = Gp[a][j] = Gm[a][j] = 0.0;
-        flux_v_acc(up, gp, gas, 0.5, Fv);
-        flux_v_acc(um, gm, gas, 0.5, Fv);
-        flux_v_acc(up, X, gas, -0.5, Gp);     // G+ = 1/2 K(u+)(n+ (x) [u]) = -1/2 F_v(u+, [u] (x) n+)
-        flux_v_acc(um, X, gas, -0.5, Gm);
-        const double cp = 0.5 * gas.eta * lam_p, cm = 0.5 * gas.eta * lam_m;
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            T fn = 0.0;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) fn = fn + (Fv[a][j] + cp * Gp[a][j] + cm * Gm[a][j]) * nrm[j];
-            fo[a] = sc * (Fh[a] + fn);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                fo[5 + a * 3 + k] = -sc * (Jip[k][0] * Gp[a][0] + Jip[k][1] * Gp[a][1] + Jip[k][2] * Gp[a][2]);
+                for (int j = 0; j < 3; ++j)
+                    g[a][j] = Jim[0][j] * gxm[a][0] + Jim[1][j] * gxm[a][1] + Jim[2][j] * gxm[a][2];
+            flux_v_n_acc(um, g, gas, 0.5, nrm, Fn);
         }
+        face_penalty_symmetry<T>(up, um, nrm, Jip, lam_p, lam_m, sc, gas, Fn, fo);
     } else {
 #pragma unroll
-        for (int a = 0; a < 5; ++a) fo[a] = sc * Fh[a];
+        for (int a = 0; a < 5; ++a) fo[a] = sc * Fn[a];
     }
 }
 
@@ -217,6 +274,8 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
                                            const double* __restrict__ hbuf, double shift, double* __restrict__ out,
                                            T* S, double* sdet, double* svtx, int e, bool active, int q) {
     using S_ = Sz<P>;
+    using L_ = LayOf<P, MODE>;
+    constexpr bool UP = FaceMode<P, MODE>::UP;
     constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = S_::NB;
     constexpr bool DUAL = (MODE >= M_TANGENT);
     const Tab& tb = c_tab[P];
@@ -246,8 +305,8 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
     // ---- interpolation to the Gauss points ---------------------------------------
     T* X1 = S + 5 * NQ;
     T* X2 = S + 10 * NQ;
-    T* su = S + S_::OFF_U;
-    T* sg = S + S_::OFF_G;
+    T* su = S + L_::OFF_U;
+    T* sg = S + L_::OFF_G;        // UP only
     if (active) sweep<N, 5, false>(tb.V, S, X1, 0, ii, q);
     __syncthreads();
     if (active) sweep<N, 5, false>(tb.V, X1, X2, 1, ii, q);
@@ -270,7 +329,7 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
 #pragma unroll
                 for (int j = 0; j < N; ++j) acc = fma(tb.D[ii[k]][j], su[a * NQ + tix_dir<N>(k, j, ii)], acc);
                 gx[a][k] = acc;
-                sg[(a * 3 + k) * NQ + q] = acc;
+                if constexpr (UP) sg[(a * 3 + k) * NQ + q] = acc;
             }
         }
         if constexpr (CURVED) {
@@ -311,185 +370,409 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
     }
     __syncthreads();
 
-    // ---- faces ------------------------------------------------------------------
-    T* sC = S;                    // collapse of the neighbour modal data (60 NF)
-    T* sE = S + S_::OFF_E;        // after the first tangential sweep (90 NF)
-    T* sF = S + S_::OFF_F;        // face integrands (120 NF)
-    if (active) {
-        for (int fp = q; fp < 6 * NF; fp += NQ) {
-            const int f = fp / NF, fq = fp % NF;
-            const int d = f >> 1, s = f & 1;
-            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
-            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
-            const int nb = nbr_of(m, e, f);
-            const size_t nbase = (size_t)nb * NB;
-            const int tb0 = (fq / N) * st1 + (fq % N) * st2;
+    if constexpr (UP) {
+        // ---- faces (all neighbour data collapsed up front) ----------------------------
+        T* sC = S;                    // collapse of the neighbour modal data (60 NF)
+        T* sE = S + L_::OFF_E;        // after the first tangential sweep (90 NF)
+        T* sF = S;                    // face integrands of one round (20 NQ; the collapse is dead by then)
+        if (active) {
+            for (int fp = q; fp < 6 * NF; fp += NQ) {
+                const int f = fp / NF, fq = fp % NF;
+                const int d = f >> 1, s = f & 1;
+                const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+                const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+                const int nb = nbr_of(m, e, f);
+                const size_t nbase = (size_t)nb * NB;
+                const int tb0 = (fq / N) * st1 + (fq % N) * st2;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                T c0 = 0.0, c1 = 0.0;
+                for (int a = 0; a < 5; ++a) {
+                    T c0 = 0.0, c1 = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const int pm = perm[tb0 + k * sd];
-                    const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm);
-                    c0 = fma(tb.Le[1 - s][k], val, c0);
-                    c1 = fma(tb.Lde[1 - s][k], val, c1);
+                    for (int k = 0; k < N; ++k) {
+                        const int pm = perm[tb0 + k * sd];
+                        const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm);
+                        c0 = fma(tb.Le[1 - s][k], val, c0);
+                        c1 = fma(tb.Lde[1 - s][k], val, c1);
+                    }
+                    sC[(f * NF + fq) * 10 + a * 2 + 0] = c0;
+                    sC[(f * NF + fq) * 10 + a * 2 + 1] = c1;
                 }
-                sC[(f * NF + fq) * 10 + a * 2 + 0] = c0;
-                sC[(f * NF + fq) * 10 + a * 2 + 1] = c1;
             }
         }
-    }
-    __syncthreads();
-    if (active) {
-        for (int fp = q; fp < 6 * NF; fp += NQ) {
-            const int f = fp / NF, fq = fp % NF;
-            const int qt1 = fq / N, cc = fq % N;
+        __syncthreads();
+        if (active) {
+            for (int fp = q; fp < 6 * NF; fp += NQ) {
+                const int f = fp / NF, fq = fp % NF;
+                const int qt1 = fq / N, cc = fq % N;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                T e0 = 0.0, e0d = 0.0, e1 = 0.0;
+                for (int a = 0; a < 5; ++a) {
+                    T e0 = 0.0, e0d = 0.0, e1 = 0.0;
 #pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const T* cb = sC + (f * NF + b * N + cc) * 10 + a * 2;
-                    e0 = fma(tb.V[qt1][b], cb[0], e0);
-                    e0d = fma(tb.Vd[qt1][b], cb[0], e0d);
-                    e1 = fma(tb.V[qt1][b], cb[1], e1);
+                    for (int b = 0; b < N; ++b) {
+                        const T* cb = sC + (f * NF + b * N + cc) * 10 + a * 2;
+                        e0 = fma(tb.V[qt1][b], cb[0], e0);
+                        e0d = fma(tb.Vd[qt1][b], cb[0], e0d);
+                        e1 = fma(tb.V[qt1][b], cb[1], e1);
+                    }
+                    T* eo = sE + (f * NF + fq) * 15 + a * 3;
+                    eo[0] = e0;
+                    eo[1] = e0d;
+                    eo[2] = e1;
                 }
-                T* eo = sE + (f * NF + fq) * 15 + a * 3;
-                eo[0] = e0;
-                eo[1] = e0d;
-                eo[2] = e1;
             }
         }
-    }
-    __syncthreads();
-    if (active) {
-        for (int fp = q; fp < 6 * NF; fp += NQ) {
-            const int f = fp / NF, fq = fp % NF;
+        __syncthreads();
+        for (int r = 0; r * NQ < 6 * NF; ++r) {
+            const int fp = r * NQ + q;
+            if (active && fp < 6 * NF) {
+                const int f = fp / NF, fq = fp % NF;
+                const int d = f >> 1, s = f & 1;
+                const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+                const int qt1 = fq / N, qt2 = fq % N;
+                const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+                const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+                T um[5], gxm[5][3], up[5], gxp[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    T v0 = 0.0, vt1 = 0.0, vt2 = 0.0, vd = 0.0;
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        const T* eo = sE + (f * NF + qt1 * N + c) * 15 + a * 3;
+                        v0 = fma(tb.V[qt2][c], eo[0], v0);
+                        vt1 = fma(tb.V[qt2][c], eo[1], vt1);
+                        vt2 = fma(tb.Vd[qt2][c], eo[0], vt2);
+                        vd = fma(tb.V[qt2][c], eo[2], vd);
+                    }
+                    um[a] = v0;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) gxm[a][kk] = (kk == d) ? vd : ((kk == t1) ? vt1 : vt2);
+                }
+                const int tl = qt1 * st1 + qt2 * st2;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    T v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        const int t = tl + k * sd;
+                        const double l = tb.lag[s][k];
+                        v0 = fma(l, su[a * NQ + t], v0);
+                        g0 = fma(l, sg[(a * 3 + 0) * NQ + t], g0);
+                        g1 = fma(l, sg[(a * 3 + 1) * NQ + t], g1);
+                        g2 = fma(l, sg[(a * 3 + 2) * NQ + t], g2);
+                    }
+                    up[a] = v0;
+                    gxp[a][0] = g0;
+                    gxp[a][1] = g1;
+                    gxp[a][2] = g2;
+                }
+                // geometry of the face point seen from both sides
+                double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
+                const double sgn = s ? 1.0 : -1.0;
+                if constexpr (CURVED) {
+                    const double z1 = tb.z[qt1], z2 = tb.z[qt2];
+                    double xi[3];
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
+                    double J[3][3];
+                    q1_jac(svtx, xi[0], xi[1], xi[2], J);
+                    q1_inv(J, Jip);
+                    // tangents dx/dxi_{d+1}, dx/dxi_{d+2} (cyclic): their cross product points to +xi_d
+                    const int da = (d + 1) % 3, db = (d + 2) % 3;
+                    double ta[3], tbv[3];
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        ta[kk] = (da == 0) ? J[kk][0] : ((da == 1) ? J[kk][1] : J[kk][2]);
+                        tbv[kk] = (db == 0) ? J[kk][0] : ((db == 1) ? J[kk][1] : J[kk][2]);
+                    }
+                    const double cx = ta[1] * tbv[2] - ta[2] * tbv[1];
+                    const double cy = ta[2] * tbv[0] - ta[0] * tbv[2];
+                    const double cz = ta[0] * tbv[1] - ta[1] * tbv[0];
+                    JF = sqrt(cx * cx + cy * cy + cz * cz);
+                    nrm[0] = sgn * cx / JF;
+                    nrm[1] = sgn * cy / JF;
+                    nrm[2] = sgn * cz / JF;
+                    const double* vn = m.vtx + (size_t)nbr_of(m, e, f) * 24;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? -sgn : ((kk == t1) ? z1 : z2);
+                    q1_jac(vn, xi[0], xi[1], xi[2], J);
+                    q1_inv(J, Jim);
+                    double sp = 0.0, sm = 0.0;
+                    for (int k = 0; k < N; ++k) {
+                        sp += tb.br2[s][k] / sdet[tl + k * sd];
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
+                        q1_jac(vn, xi[0], xi[1], xi[2], J);
+                        sm += tb.br2[1 - s][k] / q1_det(J);
+                    }
+                    lam_p = JF * sp;
+                    lam_m = JF * sm;
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) nrm[kk] = (kk == d) ? sgn : 0.0;
+                    JF = 0.25 * ((d == 0) ? hy * hz : ((d == 1) ? hx * hz : hx * hy));
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int dd = 0; dd < 3; ++dd) Jip[k][dd] = 0.0;
+                    Jip[0][0] = 2.0 / hx;
+                    Jip[1][1] = 2.0 / hy;
+                    Jip[2][2] = 2.0 / hz;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int dd = 0; dd < 3; ++dd) Jim[k][dd] = Jip[k][dd];
+                    lam_p = lam_m = 0.5 * N * N * JF / detJ;
+                }
+                face_integrand<T, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
+                                      sF + q * 20);
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int fl = 0; fl < N; ++fl) {
+                    const int f = r * N + fl;
+                    if (f >= 6) break;
+                    const int d = f >> 1, s = f & 1;
+                    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+                    const double l = tb.lag[s][ii[d]];
+                    const T* fo = sF + (fl * NF + ii[t1] * N + ii[t2]) * 20;
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) {
+                        B[a] = fma(l, fo[a], B[a]);
+                        if constexpr (NS) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) A[a][k] = fma(l, fo[5 + a * 3 + k], A[a][k]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        // ---- faces ------------------------------------------------------------------
+        // Rounds of NQ face points (N whole faces each, NQ = N NF); thread q takes
+        // slot q = (face fl of the round, face point fq) in every stage:
+        //   1  neighbour: collapse of its modal data along the normal (value and
+        //      normal derivative at the shared face) -> sC; own: trace of the
+        //      Gauss values -> sT, normal derivative of the trace (registers);
+        //   2  neighbour: first tangential sweep -> sE;
+        //   3  both traces with reference gradients (own tangential derivatives
+        //      by the collocation derivative on the face), then the face
+        //      integrand -> sF (over sC and sT);
+        //   4  spread onto the Gauss lines (faces in increasing order).
+        T* sC = S;                    // 10 per slot
+        T* sT = S + 10 * NQ;          // 5 per slot
+        T* sE = S + L_::OFF_E;        // 15 per slot
+        T* sF = S;                    // 20 per slot
+        for (int r = 0; r * NQ < 6 * NF; ++r) {
+            const int fp = r * NQ + q;
+            const bool on = active && fp < 6 * NF;
+            const int fl = q / NF, fq = q % NF;
+            const int f = on ? fp / NF : 0;
             const int d = f >> 1, s = f & 1;
             const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
             const int qt1 = fq / N, qt2 = fq % N;
             const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
             const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
-            T um[5], gxm[5][3], up[5], gxp[5][3];
-#pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                T v0 = 0.0, vt1 = 0.0, vt2 = 0.0, vd = 0.0;
-#pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    const T* eo = sE + (f * NF + qt1 * N + c) * 15 + a * 3;
-                    v0 = fma(tb.V[qt2][c], eo[0], v0);
-                    vt1 = fma(tb.V[qt2][c], eo[1], vt1);
-                    vt2 = fma(tb.Vd[qt2][c], eo[0], vt2);
-                    vd = fma(tb.V[qt2][c], eo[2], vd);
-                }
-                um[a] = v0;
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk) gxm[a][kk] = (kk == d) ? vd : ((kk == t1) ? vt1 : vt2);
-            }
             const int tl = qt1 * st1 + qt2 * st2;
+            T gdn[5];
+            if (on) {
+                const int nb = nbr_of(m, e, f);
+                const size_t nbase = (size_t)nb * NB;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                T v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+                for (int a = 0; a < 5; ++a) {
+                    T c0 = 0.0, c1 = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const int t = tl + k * sd;
-                    const double l = tb.lag[s][k];
-                    v0 = fma(l, su[a * NQ + t], v0);
-                    g0 = fma(l, sg[(a * 3 + 0) * NQ + t], g0);
-                    g1 = fma(l, sg[(a * 3 + 1) * NQ + t], g1);
-                    g2 = fma(l, sg[(a * 3 + 2) * NQ + t], g2);
+                    for (int k = 0; k < N; ++k) {
+                        const int pm = perm[tl + k * sd];
+                        const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm);
+                        c0 = fma(tb.Le[1 - s][k], val, c0);
+                        c1 = fma(tb.Lde[1 - s][k], val, c1);
+                    }
+                    sC[q * 10 + a * 2 + 0] = c0;
+                    sC[q * 10 + a * 2 + 1] = c1;
+                    T v0 = 0.0, v1 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        const T uk = su[a * NQ + tl + k * sd];
+                        v0 = fma(tb.lag[s][k], uk, v0);
+                        v1 = fma(tb.lagd[s][k], uk, v1);
+                    }
+                    sT[q * 5 + a] = v0;
+                    gdn[a] = v1;
                 }
-                up[a] = v0;
-                gxp[a][0] = g0;
-                gxp[a][1] = g1;
-                gxp[a][2] = g2;
             }
-            // geometry of the face point seen from both sides
-            double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
-            const double sgn = s ? 1.0 : -1.0;
-            if constexpr (CURVED) {
-                const double z1 = tb.z[qt1], z2 = tb.z[qt2];
-                double xi[3];
+            __syncthreads();
+            if (on) {
+                const int cc = qt2;
 #pragma unroll
-                for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
-                double J[3][3];
-                q1_jac(svtx, xi[0], xi[1], xi[2], J);
-                q1_inv(J, Jip);
-                // tangents dx/dxi_{d+1}, dx/dxi_{d+2} (cyclic): their cross product points to +xi_d
-                const int da = (d + 1) % 3, db = (d + 2) % 3;
-                double ta[3], tbv[3];
+                for (int a = 0; a < 5; ++a) {
+                    T e0 = 0.0, e0d = 0.0, e1 = 0.0;
 #pragma unroll
-                for (int kk = 0; kk < 3; ++kk) {
-                    ta[kk] = (da == 0) ? J[kk][0] : ((da == 1) ? J[kk][1] : J[kk][2]);
-                    tbv[kk] = (db == 0) ? J[kk][0] : ((db == 1) ? J[kk][1] : J[kk][2]);
+                    for (int b = 0; b < N; ++b) {
+                        const T* cb = sC + (fl * NF + b * N + cc) * 10 + a * 2;
+                        e0 = fma(tb.V[qt1][b], cb[0], e0);
+                        e0d = fma(tb.Vd[qt1][b], cb[0], e0d);
+                        e1 = fma(tb.V[qt1][b], cb[1], e1);
+                    }
+                    T* eo = sE + q * 15 + a * 3;
+                    eo[0] = e0;
+                    eo[1] = e0d;
+                    eo[2] = e1;
                 }
-                const double cx = ta[1] * tbv[2] - ta[2] * tbv[1];
-                const double cy = ta[2] * tbv[0] - ta[0] * tbv[2];
-                const double cz = ta[0] * tbv[1] - ta[1] * tbv[0];
-                JF = sqrt(cx * cx + cy * cy + cz * cz);
-                nrm[0] = sgn * cx / JF;
-                nrm[1] = sgn * cy / JF;
-                nrm[2] = sgn * cz / JF;
-                const double* vn = m.vtx + (size_t)nbr_of(m, e, f) * 24;
+            }
+            __syncthreads();
+            // Stage 3 evaluates the integrand into registers, each trace gradient
+            // only where it is used (short live ranges), then writes it over sC/sT.
+            T fo[20];
+            if (on) {
+                // geometry of the face point seen from both sides
+                double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
+                const double sgn = s ? 1.0 : -1.0;
+                if constexpr (CURVED) {
+                    const double z1 = tb.z[qt1], z2 = tb.z[qt2];
+                    double xi[3];
 #pragma unroll
-                for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? -sgn : ((kk == t1) ? z1 : z2);
-                q1_jac(vn, xi[0], xi[1], xi[2], J);
-                q1_inv(J, Jim);
-                double sp = 0.0, sm = 0.0;
-                for (int k = 0; k < N; ++k) {
-                    sp += tb.br2[s][k] / sdet[tl + k * sd];
+                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? sgn : ((kk == t1) ? z1 : z2);
+                    double J[3][3];
+                    q1_jac(svtx, xi[0], xi[1], xi[2], J);
+                    q1_inv(J, Jip);
+                    // tangents dx/dxi_{d+1}, dx/dxi_{d+2} (cyclic): their cross product points to +xi_d
+                    const int da = (d + 1) % 3, db = (d + 2) % 3;
+                    double ta[3], tbv[3];
 #pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
+                    for (int kk = 0; kk < 3; ++kk) {
+                        ta[kk] = (da == 0) ? J[kk][0] : ((da == 1) ? J[kk][1] : J[kk][2]);
+                        tbv[kk] = (db == 0) ? J[kk][0] : ((db == 1) ? J[kk][1] : J[kk][2]);
+                    }
+                    const double cx = ta[1] * tbv[2] - ta[2] * tbv[1];
+                    const double cy = ta[2] * tbv[0] - ta[0] * tbv[2];
+                    const double cz = ta[0] * tbv[1] - ta[1] * tbv[0];
+                    JF = sqrt(cx * cx + cy * cy + cz * cz);
+                    nrm[0] = sgn * cx / JF;
+                    nrm[1] = sgn * cy / JF;
+                    nrm[2] = sgn * cz / JF;
+                    const double* vn = m.vtx + (size_t)nbr_of(m, e, f) * 24;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? -sgn : ((kk == t1) ? z1 : z2);
                     q1_jac(vn, xi[0], xi[1], xi[2], J);
-                    sm += tb.br2[1 - s][k] / q1_det(J);
+                    q1_inv(J, Jim);
+                    double sp = 0.0, sm = 0.0;
+                    for (int k = 0; k < N; ++k) {
+                        sp += tb.br2[s][k] / sdet[tl + k * sd];
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) xi[kk] = (kk == d) ? tb.z[k] : ((kk == t1) ? z1 : z2);
+                        q1_jac(vn, xi[0], xi[1], xi[2], J);
+                        sm += tb.br2[1 - s][k] / q1_det(J);
+                    }
+                    lam_p = JF * sp;
+                    lam_m = JF * sm;
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) nrm[kk] = (kk == d) ? sgn : 0.0;
+                    JF = 0.25 * ((d == 0) ? hy * hz : ((d == 1) ? hx * hz : hx * hy));
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int dd = 0; dd < 3; ++dd) Jip[k][dd] = 0.0;
+                    Jip[0][0] = 2.0 / hx;
+                    Jip[1][1] = 2.0 / hy;
+                    Jip[2][2] = 2.0 / hz;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int dd = 0; dd < 3; ++dd) Jim[k][dd] = Jip[k][dd];
+                    lam_p = lam_m = 0.5 * N * N * JF / detJ;
                 }
-                lam_p = JF * sp;
-                lam_m = JF * sm;
-            } else {
+                T up[5], um[5];
 #pragma unroll
-                for (int kk = 0; kk < 3; ++kk) nrm[kk] = (kk == d) ? sgn : 0.0;
-                JF = 0.25 * ((d == 0) ? hy * hz : ((d == 1) ? hx * hz : hx * hy));
+                for (int a = 0; a < 5; ++a) {
+                    T v0 = 0.0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int dd = 0; dd < 3; ++dd) Jip[k][dd] = 0.0;
-                Jip[0][0] = 2.0 / hx;
-                Jip[1][1] = 2.0 / hy;
-                Jip[2][2] = 2.0 / hz;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int dd = 0; dd < 3; ++dd) Jim[k][dd] = Jip[k][dd];
-                lam_p = lam_m = 0.5 * N * N * JF / detJ;
-            }
-            face_integrand<T, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
-                                  sF + (f * NF + fq) * 20);
-        }
-    }
-    __syncthreads();
-    // ---- spread face integrands onto the Gauss lines --------------------------------------
-    if (active) {
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int d = f >> 1, s = f & 1;
-            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-            const double l = tb.lag[s][ii[d]];
-            const T* fo = sF + (f * NF + ii[t1] * N + ii[t2]) * 20;
-#pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                B[a] = fma(l, fo[a], B[a]);
+                    for (int c = 0; c < N; ++c) v0 = fma(tb.V[qt2][c], sE[(fl * NF + qt1 * N + c) * 15 + a * 3], v0);
+                    um[a] = v0;
+                    up[a] = sT[q * 5 + a];
+                }
+                T Fn[5];
+                roe_flux(up, um, nrm, gas.gamma, Fn);
+                const double sc = tb.w[qt1] * tb.w[qt2] * JF;
                 if constexpr (NS) {
+                    {   // + side: reference gradient of the own trace -> physical -> normal viscous flux
+                        T g[5][3];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) A[a][k] = fma(l, fo[5 + a * 3 + k], A[a][k]);
+                        for (int a = 0; a < 5; ++a) {
+                            T o1 = 0.0, o2 = 0.0;
+#pragma unroll
+                            for (int c = 0; c < N; ++c) {
+                                o1 = fma(tb.D[qt1][c], sT[(fl * NF + c * N + qt2) * 5 + a], o1);
+                                o2 = fma(tb.D[qt2][c], sT[(fl * NF + qt1 * N + c) * 5 + a], o2);
+                            }
+                            T gx[3];
+#pragma unroll
+                            for (int kk = 0; kk < 3; ++kk) gx[kk] = (kk == d) ? gdn[a] : ((kk == t1) ? o1 : o2);
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) g[a][j] = Jip[0][j] * gx[0] + Jip[1][j] * gx[1] + Jip[2][j] * gx[2];
+                        }
+                        flux_v_n_acc(up, g, gas, 0.5, nrm, Fn);
+                    }
+                    {   // - side: neighbour trace gradient from the tangential sweep
+                        T g[5][3];
+#pragma unroll
+                        for (int a = 0; a < 5; ++a) {
+                            T vt1 = 0.0, vt2 = 0.0, vd = 0.0;
+#pragma unroll
+                            for (int c = 0; c < N; ++c) {
+                                const T* eo = sE + (fl * NF + qt1 * N + c) * 15 + a * 3;
+                                vt1 = fma(tb.V[qt2][c], eo[1], vt1);
+                                vt2 = fma(tb.Vd[qt2][c], eo[0], vt2);
+                                vd = fma(tb.V[qt2][c], eo[2], vd);
+                            }
+                            T gx[3];
+#pragma unroll
+                            for (int kk = 0; kk < 3; ++kk) gx[kk] = (kk == d) ? vd : ((kk == t1) ? vt1 : vt2);
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) g[a][j] = Jim[0][j] * gx[0] + Jim[1][j] * gx[1] + Jim[2][j] * gx[2];
+                        }
+                        flux_v_n_acc(um, g, gas, 0.5, nrm, Fn);
+                    }
+                    face_penalty_symmetry<T>(up, um, nrm, Jip, lam_p, lam_m, sc, gas, Fn, fo);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) fo[a] = sc * Fn[a];
                 }
             }
+            __syncthreads();
+            if (on) {
+#pragma unroll
+                for (int k = 0; k < (NS ? 20 : 5); ++k) sF[q * 20 + k] = fo[k];
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int fl2 = 0; fl2 < N; ++fl2) {
+                    const int f2 = r * N + fl2;
+                    if (f2 >= 6) break;
+                    const int d2 = f2 >> 1, s2 = f2 & 1;
+                    const int u1 = (d2 == 0) ? 1 : 0, u2 = (d2 == 2) ? 1 : 2;
+                    const double l = tb.lag[s2][ii[d2]];
+                    const T* fo = sF + (fl2 * NF + ii[u1] * N + ii[u2]) * 20;
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) {
+                        B[a] = fma(l, fo[a], B[a]);
+                        if constexpr (NS) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) A[a][k] = fma(l, fo[5 + a * 3 + k], A[a][k]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
     // ---- test: R = V^T (x) V^T (x) V^T [B + sum_k D_k^T A_k] -------------------------------
     T* sA = S;                    // 15 NQ
     T* sB = S + 15 * NQ;          // 5 NQ
-    T* H = S + S_::OFF_E;
+    T* H = S + L_::OFF_E;
     T* Y1 = H + 5 * NQ;
     T* Y2 = H + 10 * NQ;
     if (active) {
@@ -590,8 +873,13 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
     }
 }
 
+// Two waves per SIMD where the registers allow it without spilling (straight
+// elements, real arithmetic, degree <= 3); one otherwise.
+template <int P, bool CURVED, int MODE>
+struct MinWaves { static constexpr int W = (MODE < M_TANGENT && P <= 3 && !CURVED) ? 2 : 1; };
+
 template <int P, bool NS, bool CURVED, int MODE>
-__global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ))
+__global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::NQ), (MinWaves<P, CURVED, MODE>::W))
     dg_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ V,
               const double* __restrict__ RW, const double* __restrict__ hbuf, double shift,
               double* __restrict__ out) {
@@ -600,12 +888,13 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
     constexpr bool DUAL = (MODE >= M_TANGENT);
     using T = typename std::conditional<DUAL, Dual, double>::type;
     constexpr int EPB = Launch<P, DUAL>::EPB;
-    __shared__ T smem[EPB * S_::TOT];
+    __shared__ T smem[EPB * LayOf<P, MODE>::TOT];
     __shared__ double sdet[EPB][NQ];
     __shared__ double svtx[EPB][24];
     const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
     const int e = blockIdx.x * EPB + es;
-    dg_element<P, NS, CURVED, MODE>(m, gas, W, V, RW, hbuf, shift, out, smem + es * S_::TOT, sdet[es], svtx[es], e,
+    dg_element<P, NS, CURVED, MODE>(m, gas, W, V, RW, hbuf, shift, out, smem + es * LayOf<P, MODE>::TOT, sdet[es],
+                                    svtx[es], e,
                                     e < m.ne, q);
 }
 
@@ -850,12 +1139,13 @@ hipError_t launch_check_jacobian(const DGArgs& a, int* bad, hipStream_t s) {
 // NQ threads per element) and moves on; results are per element, so they do
 // not depend on the tiling or the grid.
 size_t batch_slot_bytes(int p, int mode) {
-    const size_t sc = (mode == M_TANGENT) ? sizeof(Dual) : sizeof(double);
+    const bool dual = mode == M_TANGENT;
+    const size_t sc = dual ? sizeof(Dual) : sizeof(double);
     switch (p) {
-        case 1: return Sz<1>::TOT * sc + (Sz<1>::NQ + 24) * sizeof(double);
-        case 2: return Sz<2>::TOT * sc + (Sz<2>::NQ + 24) * sizeof(double);
-        case 3: return Sz<3>::TOT * sc + (Sz<3>::NQ + 24) * sizeof(double);
-        case 4: return Sz<4>::TOT * sc + (Sz<4>::NQ + 24) * sizeof(double);
+        case 1: return (dual ? LayOf<1, M_TANGENT>::TOT : LayOf<1, M_RES>::TOT) * sc + (Sz<1>::NQ + 24) * sizeof(double);
+        case 2: return (dual ? LayOf<2, M_TANGENT>::TOT : LayOf<2, M_RES>::TOT) * sc + (Sz<2>::NQ + 24) * sizeof(double);
+        case 3: return (dual ? LayOf<3, M_TANGENT>::TOT : LayOf<3, M_RES>::TOT) * sc + (Sz<3>::NQ + 24) * sizeof(double);
+        case 4: return (dual ? LayOf<4, M_TANGENT>::TOT : LayOf<4, M_RES>::TOT) * sc + (Sz<4>::NQ + 24) * sizeof(double);
         default: return 0;
     }
 }
@@ -871,9 +1161,10 @@ __device__ __forceinline__ void batch_tile(const BatchCaseDev& c, const BatchIte
     const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
     const bool slot = es < w.n;
     const int esl = slot ? es : 0;
-    T* S = reinterpret_cast<T*>(dyn) + (size_t)esl * S_::TOT;
-    double* sdet = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * S_::TOT) + esl * NQ;
-    double* svtx = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * S_::TOT) + w.n * NQ + esl * 24;
+    constexpr int TOT = LayOf<P, MODE>::TOT;
+    T* S = reinterpret_cast<T*>(dyn) + (size_t)esl * TOT;
+    double* sdet = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * TOT) + esl * NQ;
+    double* svtx = reinterpret_cast<double*>(reinterpret_cast<T*>(dyn) + (size_t)w.n * TOT) + w.n * NQ + esl * 24;
     const size_t o = c.off;
     const int e = w.e0 + es;
     dg_element<P, NS, CURVED, MODE>(c.m, c.g, W + o, V ? V + o : nullptr, RW ? RW + o : nullptr, hcase + w.c, shift,
@@ -1192,13 +1483,14 @@ template <>
 __device__ __forceinline__ unsigned short to_storage<unsigned short>(double v) { return bf16_rne(v); }
 
 template <class SF>
-__global__ void __launch_bounds__(256) bsr_pack_kernel(int ne, int nbc, const double* __restrict__ diag,
+__global__ void __launch_bounds__(256) bsr_pack_kernel(int ne, int nbc, int nblk, const double* __restrict__ diag,
                                                        const double* __restrict__ off, SF* __restrict__ out) {
     constexpr int W = 16 / sizeof(SF);
     const int ldr = bsr_ldr(nbc);
     const size_t nrows = (size_t)ne * nbc;
-    const size_t total = bsr_entries(ne, nbc);
-    const int nk = 7 * ldr / W;                     // 16-byte chunks per row
+    const size_t total = bsr_entries(ne, nbc, nblk);
+    const int nk = nblk * ldr / W;                  // 16-byte chunks per row
+    const int f0 = 7 - nblk;                        // 0: slot 0 is the diagonal block; 1: faces only
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const int j = (int)(i % W);
@@ -1212,7 +1504,7 @@ __global__ void __launch_bounds__(256) bsr_pack_kernel(int ne, int nbc, const do
         if (g < nrows) {
             const size_t e = g / nbc;
             const int r = (int)(g % nbc);
-            const int k = kc * W + j, f = k / ldr, c = k % ldr;
+            const int k = kc * W + j, f = k / ldr + f0, c = k % ldr;
             if (c < nbc)
                 v = (f == 0) ? diag[(e * nbc + c) * nbc + r] : off[((e * 6 + (f - 1)) * nbc + c) * nbc + r];
         }
@@ -1248,11 +1540,17 @@ __device__ __forceinline__ void bsr_chunk<unsigned short, float>(const unsigned 
     }
 }
 
-template <class SF, class AT>
+// y = K x, row g per thread.  UNIT: the stored blocks are the six face blocks
+// and the diagonal block is the identity (y = x + sum of the face terms, the
+// identity term added in FP64).
+template <class SF, class AT, bool UNIT, bool DOTS = false>
 __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const SF* __restrict__ A,
-                                                       const double* __restrict__ x, double* __restrict__ y) {
+                                                       const double* __restrict__ x, double* __restrict__ y,
+                                                       const double* __restrict__ Vb = nullptr, int k = 0,
+                                                       double* __restrict__ part = nullptr) {
+    constexpr int NBLK = UNIT ? 6 : 7;
     extern __shared__ double smraw[];
-    AT* xs = reinterpret_cast<AT*>(smraw);          // [element in range][7][ldr]
+    AT* xs = reinterpret_cast<AT*>(smraw);          // [element in range][NBLK][ldr]
     constexpr int W = 16 / sizeof(SF);
     const int ldr = bsr_ldr(nbc);
     const size_t nrows = (size_t)m.ne * nbc;
@@ -1260,29 +1558,45 @@ __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const
     const size_t glast = min(g0 + blockDim.x, nrows) - 1;
     const int e_first = (int)(g0 / nbc);
     const int nel = (int)(glast / nbc) - e_first + 1;
-    for (int i = threadIdx.x; i < nel * 7 * ldr; i += blockDim.x) {
-        const int c = i % ldr, t = i / ldr, f = t % 7, le = t / 7;
+    for (int i = threadIdx.x; i < nel * NBLK * ldr; i += blockDim.x) {
+        const int c = i % ldr, t = i / ldr, f = t % NBLK, le = t / NBLK;
         const int e = e_first + le;
-        const int src = (f == 0) ? e : nbr_of(m, e, f - 1);
+        const int src = UNIT ? nbr_of(m, e, f) : ((f == 0) ? e : nbr_of(m, e, f - 1));
         xs[i] = (c < nbc) ? (AT)x[(size_t)src * nbc + c] : (AT)0;
     }
     __syncthreads();
     const size_t g = g0 + threadIdx.x;
-    if (g >= nrows) return;
-    const int e = (int)(g / nbc);
-    const AT* xe = xs + (size_t)(e - e_first) * 7 * ldr;
-    const int nk = 7 * ldr / W;
-    const SF* base = A + ((g / 64) * (size_t)nk * 64 + (g % 64)) * W;
-    AT acc = 0;
-    for (int kc = 0; kc < nk; ++kc) bsr_chunk<SF, AT>(base + (size_t)kc * 64 * W, xe + kc * W, acc);
-    y[g] = (double)acc;
+    double yg = 0.0;
+    if (g < nrows) {
+        const int e = (int)(g / nbc);
+        const AT* xe = xs + (size_t)(e - e_first) * NBLK * ldr;
+        const int nk = NBLK * ldr / W;
+        const SF* base = A + ((g / 64) * (size_t)nk * 64 + (g % 64)) * W;
+        AT acc = 0;
+        for (int kc = 0; kc < nk; ++kc) bsr_chunk<SF, AT>(base + (size_t)kc * 64 * W, xe + kc * W, acc);
+        yg = UNIT ? x[g] + (double)acc : (double)acc;
+        y[g] = yg;
+    }
+    if constexpr (DOTS) {
+        // first Gram-Schmidt pass of the Arnoldi step on this block's rows
+        constexpr int CH = 16;
+        __shared__ double sh[4 * CH];
+        for (int c0 = 0; c0 < k; c0 += CH) {
+            double dv[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                dv[c] = (g < nrows && c0 + c < k) ? Vb[(size_t)(c0 + c) * nrows + g] * yg : 0.0;
+            block_sum_cols<CH>(dv, min(CH, k - c0), sh, part + (size_t)c0 * gridDim.x + blockIdx.x, gridDim.x);
+        }
+    }
 }
 
 template <class SF>
-hipError_t launch_bsr_pack(const double* diag, const double* off, SF* out, int ne, int nbc, hipStream_t s) {
-    const size_t total = bsr_entries(ne, nbc);
+hipError_t launch_bsr_pack(const double* diag, const double* off, SF* out, int ne, int nbc, int nblk, hipStream_t s) {
+    if (nblk != 6 && nblk != 7) return hipErrorInvalidValue;
+    const size_t total = bsr_entries(ne, nbc, nblk);
     const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(bsr_pack_kernel<SF>, dim3(grid), dim3(256), 0, s, ne, nbc, diag, off, out);
+    hipLaunchKernelGGL(bsr_pack_kernel<SF>, dim3(grid), dim3(256), 0, s, ne, nbc, nblk, diag, off, out);
     return hipGetLastError();
 }
 
@@ -1292,12 +1606,78 @@ hipError_t launch_bsr7(const DGArgs& a, const SF* A, const double* x, double* y,
     const size_t nrows = (size_t)a.m.ne * nbc;
     const unsigned grid = (unsigned)((nrows + 255) / 256);
     const size_t lds = (size_t)(256 / nbc + 2) * 7 * bsr_ldr(nbc) * sizeof(AT);
-    hipLaunchKernelGGL((bsr_rows_kernel<SF, AT>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y);
+    hipLaunchKernelGGL((bsr_rows_kernel<SF, AT, false>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y);
     return hipGetLastError();
 }
-template hipError_t launch_bsr_pack<double>(const double*, const double*, double*, int, int, hipStream_t);
-template hipError_t launch_bsr_pack<float>(const double*, const double*, float*, int, int, hipStream_t);
-template hipError_t launch_bsr_pack<unsigned short>(const double*, const double*, unsigned short*, int, int,
+
+template <class SF>
+hipError_t launch_bsr_unit(const DGArgs& a, const SF* A, const double* x, double* y, int nbc, hipStream_t s) {
+    using AT = typename std::conditional<std::is_same<SF, unsigned short>::value, float, double>::type;
+    const size_t nrows = (size_t)a.m.ne * nbc;
+    const unsigned grid = (unsigned)((nrows + 255) / 256);
+    const size_t lds = (size_t)(256 / nbc + 2) * 6 * bsr_ldr(nbc) * sizeof(AT);
+    hipLaunchKernelGGL((bsr_rows_kernel<SF, AT, true>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y);
+    return hipGetLastError();
+}
+
+int bsr_grid(int ne, int nbc) { return (int)(((size_t)ne * nbc + 255) / 256); }
+
+template <class SF>
+hipError_t launch_bsr_unit_dots(const DGArgs& a, const SF* A, const double* x, double* y, int nbc, const double* Vb,
+                                int k, double* part, int* np, hipStream_t s) {
+    using AT = typename std::conditional<std::is_same<SF, unsigned short>::value, float, double>::type;
+    const unsigned grid = (unsigned)bsr_grid(a.m.ne, nbc);
+    const size_t lds = (size_t)(256 / nbc + 2) * 6 * bsr_ldr(nbc) * sizeof(AT);
+    hipLaunchKernelGGL((bsr_rows_kernel<SF, AT, true, true>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y, Vb, k,
+                       part);
+    *np = (int)grid;
+    return hipGetLastError();
+}
+template hipError_t launch_bsr_unit_dots<double>(const DGArgs&, const double*, const double*, double*, int,
+                                                 const double*, int, double*, int*, hipStream_t);
+template hipError_t launch_bsr_unit_dots<float>(const DGArgs&, const float*, const double*, double*, int,
+                                                const double*, int, double*, int*, hipStream_t);
+template hipError_t launch_bsr_unit_dots<unsigned short>(const DGArgs&, const unsigned short*, const double*, double*,
+                                                         int, const double*, int, double*, int*, hipStream_t);
+
+// Right-preconditioned coarse operator K D^-1: every face block K_{e,f} is
+// replaced by K_{e,f} X_{nb(e,f)}, X the neighbour's block-Jacobi inverse (the
+// diagonal K_ee X_e is the identity).  In place, column-major nbc x nbc,
+// one workgroup per (element, face), nbc <= FOLD_MAX_N.
+template <class TX>
+__global__ void __launch_bounds__(256) fold_inverse_kernel(MeshDev m, int nbc, double* __restrict__ off,
+                                                           const TX* __restrict__ X) {
+    __shared__ double sk[FOLD_MAX_N * FOLD_MAX_N];
+    const int e = blockIdx.x / 6, f = blockIdx.x % 6;
+    const size_t nn = (size_t)nbc * nbc;
+    double* K = off + ((size_t)e * 6 + f) * nn;
+    const TX* Xn = X + (size_t)nbr_of(m, e, f) * nn;
+    for (int i = threadIdx.x; i < (int)nn; i += blockDim.x) sk[i] = K[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < (int)nn; i += blockDim.x) {
+        const int r = i % nbc, c = i / nbc;
+        const TX* xc = Xn + (size_t)c * nbc;
+        double acc = 0.0;
+        for (int k = 0; k < nbc; ++k) acc = fma(sk[k * nbc + r], (double)xc[k], acc);
+        K[i] = acc;
+    }
+}
+
+template <class TX>
+hipError_t launch_fold_inverse(const DGArgs& a, int nbc, double* off, const TX* X, hipStream_t s) {
+    if (nbc < 1 || nbc > FOLD_MAX_N) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fold_inverse_kernel<TX>, dim3((unsigned)a.m.ne * 6), dim3(256), 0, s, a.m, nbc, off, X);
+    return hipGetLastError();
+}
+template hipError_t launch_fold_inverse<double>(const DGArgs&, int, double*, const double*, hipStream_t);
+template hipError_t launch_fold_inverse<float>(const DGArgs&, int, double*, const float*, hipStream_t);
+template hipError_t launch_bsr_unit<double>(const DGArgs&, const double*, const double*, double*, int, hipStream_t);
+template hipError_t launch_bsr_unit<float>(const DGArgs&, const float*, const double*, double*, int, hipStream_t);
+template hipError_t launch_bsr_unit<unsigned short>(const DGArgs&, const unsigned short*, const double*, double*,
+                                                    int, hipStream_t);
+template hipError_t launch_bsr_pack<double>(const double*, const double*, double*, int, int, int, hipStream_t);
+template hipError_t launch_bsr_pack<float>(const double*, const double*, float*, int, int, int, hipStream_t);
+template hipError_t launch_bsr_pack<unsigned short>(const double*, const double*, unsigned short*, int, int, int,
                                                     hipStream_t);
 template hipError_t launch_bsr7<double>(const DGArgs&, const double*, const double*, double*, int, hipStream_t);
 template hipError_t launch_bsr7<float>(const DGArgs&, const float*, const double*, double*, int, hipStream_t);

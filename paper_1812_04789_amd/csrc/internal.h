@@ -25,6 +25,7 @@ struct Tab {
     double w[MAXN];           // Gauss weights
     double z[MAXN];           // Gauss points
     double lag[2][MAXN];      // l_q(-1), l_q(+1): Lagrange basis of the Gauss points at the ends
+    double lagd[2][MAXN];     // l_q'(-1), l_q'(+1)
     double Le[2][MAXN];       // L_a(-1), L_a(+1)
     double Lde[2][MAXN];      // L_a'(-1), L_a'(+1)
     double br2[2][MAXN];      // (sum_i L_i(+-1) L_i(z_q))^2 w_q: BR2 line weights
@@ -134,9 +135,14 @@ hipError_t launch_prolong_add(int ne, int nvf, int nvc, const double* coarse, do
 hipError_t launch_count_nonfinite(size_t n, const double* x, int* flag, hipStream_t s);
 // One Arnoldi step j (basis V[0..j], new vector in V[j+1]): classical
 // Gram-Schmidt twice, H column j, norm, Givens rotation j, normalisation;
-// est = |g_{j+1}|.  j + 1 <= 64.
+// est = |g_{j+1}|.  j + 1 <= 64.  partial: 3 * 64 * RED_BLOCKS doubles.
 hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
                                double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s);
+// The same step when the first-pass partial dots V_i . w (i <= j) are already
+// in partial[i * np_a + b], b < np_a <= RED_BLOCKS (launch_bsr_unit_dots).
+hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* h2,
+                                          double* cs, double* sn, double* g, double* nrm, double* est,
+                                          double* partial, int np_a, hipStream_t s);
 
 // ---- dense block kernels (lu_kernels.hip) ------------------------------------
 template <class TF>
@@ -165,17 +171,33 @@ template <class TF>
 hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);
 // Block-sparse product y = K x with 7 blocks per element row (diagonal + 6
 // faces), stored sliced row-major: rows padded to bsr_ldr(nbc) entries per
-// block, grouped by 64 rows, 16-byte chunks of a group contiguous.
+// block, grouped by 64 rows, 16-byte chunks of a group contiguous.  With
+// nblk = 6 only the face blocks are stored and the diagonal is the identity.
 __host__ __device__ inline int bsr_ldr(int nbc) { return (nbc + 7) & ~7; }
-__host__ __device__ inline size_t bsr_entries(int ne, int nbc) {
-    return ((size_t)ne * nbc + 63) / 64 * 64 * 7 * (size_t)bsr_ldr(nbc);
+__host__ __device__ inline size_t bsr_entries(int ne, int nbc, int nblk = 7) {
+    return ((size_t)ne * nbc + 63) / 64 * 64 * (size_t)nblk * (size_t)bsr_ldr(nbc);
 }
-// Pack the column-major diagonal [e][c][r] and face blocks [e][f][c][r] (FP64)
-// into that layout, rounding to TF (BF16: round to nearest even).
+// Pack the column-major diagonal [e][c][r] (nblk = 7) and face blocks
+// [e][f][c][r] (FP64) into that layout, rounding to TF (BF16: nearest even).
 template <class TF>
-hipError_t launch_bsr_pack(const double* diag, const double* off, TF* out, int ne, int nbc, hipStream_t s);
+hipError_t launch_bsr_pack(const double* diag, const double* off, TF* out, int ne, int nbc, int nblk, hipStream_t s);
 template <class TF>
 hipError_t launch_bsr7(const DGArgs& a, const TF* A, const double* x, double* y, int nbc, hipStream_t s);
+// y = x + sum_f F_{e,f} x_{nb(e,f)} over the six packed face blocks (nblk = 6).
+template <class TF>
+hipError_t launch_bsr_unit(const DGArgs& a, const TF* A, const double* x, double* y, int nbc, hipStream_t s);
+// The same product, then the per-block partial dots of y with the k basis
+// vectors Vb (stride ne nbc): part[c * np + b], c < k; np (the product's
+// grid) is returned.  Deterministic (the grid depends only on ne nbc).
+template <class TF>
+hipError_t launch_bsr_unit_dots(const DGArgs& a, const TF* A, const double* x, double* y, int nbc, const double* Vb,
+                                int k, double* part, int* np, hipStream_t s);
+int bsr_grid(int ne, int nbc);
+// Face blocks [e][f][c][r] (FP64, in place) <- K_{e,f} X_{nb(e,f)}, X the
+// column-major block inverses [e][c][r]; nbc <= FOLD_MAX_N.
+constexpr int FOLD_MAX_N = 64;
+template <class TX>
+hipError_t launch_fold_inverse(const DGArgs& a, int nbc, double* off, const TX* X, hipStream_t s);
 hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s);
 hipError_t launch_convert_fp64_to_bf16(const double* x, unsigned short* y, size_t n, hipStream_t s);
 

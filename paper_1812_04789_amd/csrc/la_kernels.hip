@@ -7,6 +7,7 @@
 // a fixed tree.  Results are bitwise reproducible run to run and independent
 // of what else shares the device.
 #include "internal.h"
+#include "reduce.h"
 
 namespace dg {
 
@@ -14,45 +15,6 @@ namespace {
 constexpr int KCH = 8;    // dot products per pass of the multi-dot
 constexpr int GS_MAXK = 64;   // largest Krylov basis handled by the Arnoldi / back-solve kernels
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;       // the butterfly leaves the same sum in every lane
-}
-
-// Block sum (blockDim.x a multiple of 64): butterfly inside each wavefront,
-// then the wavefront partials in wavefront order.  Every thread gets the sum.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    const int nw = blockDim.x >> 6;
-    for (int i = 0; i < nw; ++i) r += sh[i];
-    __syncthreads();
-    return r;
-}
-
-// Block sums of kn <= K accumulators at once (one barrier pair for all):
-// thread c < kn writes the sum of acc[c] to out[c * ostride].
-template <int K>
-__device__ __forceinline__ void block_sum_cols(const double (&acc)[K], int kn, double* sh, double* out,
-                                               size_t ostride) {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int c = 0; c < K; ++c)
-        if (c < kn) {
-            const double v = wave_sum(acc[c]);
-            if ((threadIdx.x & 63) == 0) sh[w * K + c] = v;
-        }
-    __syncthreads();
-    if ((int)threadIdx.x < kn) {
-        double r = 0.0;
-        for (int i = 0; i < nw; ++i) r += sh[i * K + threadIdx.x];
-        out[threadIdx.x * ostride] = r;
-    }
-    __syncthreads();
-}
 }  // namespace
 
 __global__ void __launch_bounds__(RED_THREADS)
@@ -248,27 +210,6 @@ hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipS
 }
 
 // ---- GMRES small dense algebra on the device ---------------------------------------------
-// Hessenberg column j (length j+2) in Hc (ld = restart+1, column-major) after
-// Gram-Schmidt: apply the previous Givens rotations, build rotation j, update
-// g, store |g[j+1]| in est[0].  A single work-item (the work is O(j)).
-__global__ void givens_kernel(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est) {
-    double* h = H + (size_t)j * ldh;
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-        h[i] = t;
-    }
-    const double a = h[j], b = h[j + 1];
-    const double r = hypot(a, b);
-    const double c = (r > 0.0) ? a / r : 1.0, sgn = (r > 0.0) ? b / r : 0.0;
-    cs[j] = c;
-    sn[j] = sgn;
-    h[j] = r;
-    h[j + 1] = 0.0;
-    g[j + 1] = -sgn * g[j];
-    g[j] = c * g[j];
-    est[0] = fabs(g[j + 1]);
-}
 // y = R^-1 g[0:k] for the k x k upper triangle of H.  After a breakdown
 // (zero new direction) the trailing columns are exactly zero: they are dropped.
 __global__ void __launch_bounds__(256) backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
@@ -295,30 +236,14 @@ __global__ void __launch_bounds__(256) backsolve_kernel(const double* H, int ldh
     __syncthreads();
     for (int t = threadIdx.x; t < k; t += blockDim.x) y[t] = sy[t];
 }
-// Combine the two Gram-Schmidt passes: h[i] += h2[i] (i <= j), set h[j+1] = sqrt(nrm2) and
-// the inverse norm for normalisation.
-__global__ void gs_finish_kernel(double* hcol, const double* h2, int jp1, const double* nrm2, double* inv) {
-    for (int i = 0; i < jp1; ++i) hcol[i] += h2[i];
-    const double nr = sqrt(nrm2[0]);
-    hcol[jp1] = nr;
-    inv[0] = nr;
-}
 __global__ void init_g_kernel(double* g, int len, const double* beta2) {
     for (int i = 0; i < len; ++i) g[i] = 0.0;
     g[0] = sqrt(beta2[0]);
 }
 
-hipError_t launch_givens(double* H, int ldh, int j, double* cs, double* sn, double* g, double* est, hipStream_t s) {
-    hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, s, H, ldh, j, cs, sn, g, est);
-    return hipGetLastError();
-}
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
     if (k < 1 || k > GS_MAXK) return hipErrorInvalidValue;
     hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, s, H, ldh, k, g, y);
-    return hipGetLastError();
-}
-hipError_t launch_gs_finish(double* hcol, const double* h2, int jp1, const double* nrm2, double* nrm, hipStream_t s) {
-    hipLaunchKernelGGL(gs_finish_kernel, dim3(1), dim3(1), 0, s, hcol, h2, jp1, nrm2, nrm);
     return hipGetLastError();
 }
 hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s) {
@@ -327,21 +252,43 @@ hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s)
 }
 
 // ---- fused classical Gram-Schmidt (applied twice) for one Arnoldi step -----------------------
-// Step j, w = V[j+1], basis V[0..j]:
-//   K1  part_a = partial sums of V_i . w             (i <= j)
-//   K2  h      = sum of part_a                         -> H column j
-//   K3  w     -= sum_i h_i V_i ; part_b = V_i . w      (second pass dots)
-//   K4  h2     = sum of part_b
-//   K5  w     -= sum_i h2_i V_i ; part_c = w . w
-//   K6  (one block) h += h2, H[j+1,j] = ||w||, Givens rotation j, |g_{j+1}|
-//   K7  w     /= ||w||
-// Every sum has a fixed order: the result depends only on the data.
+// Step j, w = V[j+1], basis V[0..j]; four launches, no inter-block
+// synchronisation inside a launch:
+//   K1  pa = per-block partials of V_i . w                     (i <= j)
+//   K2  h  = sum of pa (every block; block 0 stores H column j);
+//       w -= sum_i h_i V_i ; pb = partials of V_i . w          (second pass)
+//   K3  h2 = sum of pb (every block; block 0 stores h2);
+//       w -= sum_i h2_i V_i ; pc = partials of w . w
+//   K4  nrm2 = sum of pc (every block); w /= ||w||; block 0: h += h2,
+//       H[j+1,j] = ||w||, Givens rotation j, est = |g_{j+1}|
+// Every block sums the previous launch's partials in the same fixed order,
+// so all blocks hold bitwise the same coefficients and the result depends
+// only on the data.  pa, pb, pc are disjoint (a launch reads one set while
+// writing the next).
 constexpr int GS_CH = 16;
+constexpr int GS_BLOCKS = 256;
+static_assert(3 * GS_MAXK * RED_BLOCKS <= RED_BLOCKS * 256, "the partial buffer holds three sets of partials");
 
-__global__ void __launch_bounds__(RED_THREADS)
-    gs_dots_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ w,
-                   double* __restrict__ part) {
-    __shared__ double sh[RED_THREADS];
+// out[c] = sum_{b < nparts} part[c * nparts + b] for c < k <= 64, into LDS
+// (all threads see it after the call).  A group of g threads (a power of two,
+// g k <= blockDim.x, g <= 64) takes output c: thread i of the group sums
+// b = i, i + g, ..., then the group reduces by butterfly.  The order depends
+// only on (nparts, k, blockDim.x).
+__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int nparts, int k, double* out) {
+    int g = 64;
+    while (g > 1 && g * k > (int)blockDim.x) g >>= 1;
+    const int c = threadIdx.x / g, i = threadIdx.x % g;
+    double a = 0.0;
+    if (c < k)
+        for (int b = i; b < nparts; b += g) a += part[(size_t)c * nparts + b];
+    for (int o = g >> 1; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (c < k && i == 0) out[c] = a;
+    __syncthreads();
+}
+
+// part[c * grid + block] = partial of V_c . w over this block's entries, c < k
+__device__ __forceinline__ void gs_block_dots(const double* __restrict__ V, size_t n, int k,
+                                              const double* __restrict__ w, double* __restrict__ part, double* sh) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (int c0 = 0; c0 < k; c0 += GS_CH) {
         double acc[GS_CH];
@@ -357,14 +304,23 @@ __global__ void __launch_bounds__(RED_THREADS)
     }
 }
 
-// w -= sum_i h_i V_i, then part = V_i . w (mode 0) or part = w . w (mode 1)
 __global__ void __launch_bounds__(RED_THREADS)
-    gs_update_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ h, double* __restrict__ w,
-                     double* __restrict__ part, int mode) {
+    gs_dots_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ w,
+                   double* __restrict__ pa) {
+    __shared__ double sh[RED_THREADS];
+    gs_block_dots(V, n, k, w, pa, sh);
+}
+
+// K2 / K3: coefficients from the previous partials, w -= sum_i c_i V_i, then
+// second-pass dots (mode 0, into pout) or the squared norm (mode 1).
+__global__ void __launch_bounds__(RED_THREADS)
+    gs_update_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ pin, int np_in,
+                     double* __restrict__ cout, double* __restrict__ w, double* __restrict__ pout, int mode) {
     __shared__ double sh[RED_THREADS];
     __shared__ double hs[GS_MAXK];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) hs[i] = h[i];
-    __syncthreads();
+    sum_parts(pin, np_in, k, hs);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < k; i += blockDim.x) cout[i] = hs[i];
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     if (mode == 1) {
         double nrm = 0.0;
@@ -375,39 +331,30 @@ __global__ void __launch_bounds__(RED_THREADS)
             nrm = fma(wi, wi, nrm);
         }
         const double sm = block_sum(nrm, sh);
-        if (threadIdx.x == 0) part[blockIdx.x] = sm;
+        if (threadIdx.x == 0) pout[blockIdx.x] = sm;
         return;
     }
-    // mode 0: update, then dots with the updated w in chunks of GS_CH
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wi = w[i];
         for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
         w[i] = wi;
     }
-    for (int c0 = 0; c0 < k; c0 += GS_CH) {
-        double acc[GS_CH];
-#pragma unroll
-        for (int c = 0; c < GS_CH; ++c) acc[c] = 0.0;
-        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-            const double wi = w[i];
-#pragma unroll
-            for (int c = 0; c < GS_CH; ++c)
-                if (c0 + c < k) acc[c] = fma(V[(size_t)(c0 + c) * n + i], wi, acc[c]);
-        }
-        block_sum_cols<GS_CH>(acc, min(GS_CH, k - c0), sh, part + (size_t)c0 * gridDim.x + blockIdx.x, gridDim.x);
-    }
+    gs_block_dots(V, n, k, w, pout, sh);
 }
 
-// One block: nrm2 = sum(part_c); hcol[i] += h2[i]; hcol[j+1] = ||w||; Givens j.
+// K4: ||w|| from the partials, w /= ||w||; block 0 finishes H column j and
+// the Givens rotation.
 __global__ void __launch_bounds__(RED_THREADS)
-    gs_finish_givens_kernel(const double* __restrict__ part, int nparts, double* H, int ldh, int j,
-                            const double* __restrict__ h2, double* cs, double* sn, double* g, double* nrm_out,
-                            double* est) {
-    __shared__ double sh[RED_THREADS];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
-    const double nrm2 = block_sum(acc, sh);
-    // column j, the rotations and g_j staged in LDS, then one thread rotates
+    gs_normalise_kernel(size_t n, double* __restrict__ w, const double* __restrict__ pc, double* H, int ldh, int j,
+                        const double* __restrict__ h2, double* cs, double* sn, double* g, double* nrm_out,
+                        double* est) {
+    __shared__ double s_n2;
+    sum_parts(pc, gridDim.x, 1, &s_n2);
+    const double nr = sqrt(s_n2);
+    const double a = (nr != 0.0) ? 1.0 / nr : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) w[i] = a * w[i];
+    if (blockIdx.x != 0) return;
     __shared__ double sh_h[GS_MAXK + 1], sh_c[GS_MAXK], sh_s[GS_MAXK];
     double* h = H + (size_t)j * ldh;
     for (int i = threadIdx.x; i <= j; i += blockDim.x) {
@@ -417,7 +364,6 @@ __global__ void __launch_bounds__(RED_THREADS)
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const double nr = sqrt(nrm2);
     sh_h[j + 1] = nr;
     nrm_out[0] = nr;
     for (int i = 0; i < j; ++i) {
@@ -425,9 +371,9 @@ __global__ void __launch_bounds__(RED_THREADS)
         sh_h[i + 1] = -sh_s[i] * sh_h[i] + sh_c[i] * sh_h[i + 1];
         sh_h[i] = t;
     }
-    const double a = sh_h[j], b = sh_h[j + 1];
-    const double r = hypot(a, b);
-    const double c = (r > 0.0) ? a / r : 1.0, sg = (r > 0.0) ? b / r : 0.0;
+    const double x = sh_h[j], y = sh_h[j + 1];
+    const double r = hypot(x, y);
+    const double c = (r > 0.0) ? x / r : 1.0, sg = (r > 0.0) ? y / r : 0.0;
     cs[j] = c;
     sn[j] = sg;
     sh_h[j] = r;
@@ -439,22 +385,39 @@ __global__ void __launch_bounds__(RED_THREADS)
     est[0] = fabs(g[j + 1]);
 }
 
+static hipError_t arnoldi_tail(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
+                               double* sn, double* g, double* nrm, double* est, double* partial, int np_a,
+                               hipStream_t s) {
+    const int k = j + 1;
+    const int nbk = red_blocks(n) < GS_BLOCKS ? red_blocks(n) : GS_BLOCKS;
+    double* w = const_cast<double*>(V) + (size_t)k * n;
+    double* hcol = H + (size_t)j * ldh;
+    double* pa = partial;
+    double* pb = partial + (size_t)GS_MAXK * RED_BLOCKS;
+    double* pc = partial + (size_t)2 * GS_MAXK * RED_BLOCKS;
+    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pa, np_a, hcol, w, pb, 0);
+    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pb, nbk, h2, w, pc, 1);
+    hipLaunchKernelGGL(gs_normalise_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, n, w, pc, H, ldh, j, h2, cs, sn, g,
+                       nrm, est);
+    return hipGetLastError();
+}
+
 hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
                                double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s) {
     const int k = j + 1;
     if (k > GS_MAXK) return hipErrorInvalidValue;
-    const int nbk = red_blocks(n);
+    // at most one block per CU: every block re-reads all partials of a set
+    const int nbk = red_blocks(n) < GS_BLOCKS ? red_blocks(n) : GS_BLOCKS;
     double* w = const_cast<double*>(V) + (size_t)k * n;
-    double* hcol = H + (size_t)j * ldh;
     hipLaunchKernelGGL(gs_dots_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, w, partial);
-    hipLaunchKernelGGL(sum_stage2, dim3(k), dim3(RED_THREADS), 0, s, partial, nbk, hcol);
-    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, hcol, w, partial, 0);
-    hipLaunchKernelGGL(sum_stage2, dim3(k), dim3(RED_THREADS), 0, s, partial, nbk, h2);
-    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, h2, w, partial, 1);
-    hipLaunchKernelGGL(gs_finish_givens_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, nbk, H, ldh, j, h2, cs, sn,
-                       g, nrm, est);
-    hipLaunchKernelGGL(scale_dev_kernel, grid_for(n), dim3(256), 0, s, n, w, nrm, 1, w);
-    return hipGetLastError();
+    return arnoldi_tail(V, n, j, H, ldh, h2, cs, sn, g, nrm, est, partial, nbk, s);
+}
+
+hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* h2,
+                                          double* cs, double* sn, double* g, double* nrm, double* est,
+                                          double* partial, int np_a, hipStream_t s) {
+    if (j + 1 > GS_MAXK || np_a < 1 || np_a > RED_BLOCKS) return hipErrorInvalidValue;
+    return arnoldi_tail(V, n, j, H, ldh, h2, cs, sn, g, nrm, est, partial, np_a, s);
 }
 
 // ---- per-case FD steps of a batch ------------------------------------------------------------

@@ -162,13 +162,32 @@ template hipError_t launch_extract_sub<float>(const double*, int, int, int, floa
 // ties); only the summation order of the trailing updates differs.
 constexpr int LU_NB = 16;
 
+// Largest |value| with the lowest row index on ties, over the block: a
+// butterfly inside each wavefront, then the wavefront winners in order.
+__device__ __forceinline__ int block_argmax(double v, int r, double* sv, int* sr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(v, o, 64);
+        const int r2 = __shfl_xor(r, o, 64);
+        if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sv[w] = v; sr[w] = r; }
+    __syncthreads();
+    double bv = sv[0];
+    int br = sr[0];
+    for (int i = 1; i < nw; ++i)
+        if (sv[i] > bv || (sv[i] == bv && sr[i] < br)) { bv = sv[i]; br = sr[i]; }
+    return br;
+}
+
 template <class TF>
 __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n) {
     extern __shared__ double lds[];
     double* P = lds;                      // panel, column-major with stride n: P[c*n + r], r < m
     double* U = lds + (size_t)LU_NB * n;  // U12, LU_NB x (n - k0 - kb): U[t*n + c']
-    __shared__ double rv[LU_THREADS];
-    __shared__ int ri[LU_THREADS];
+    __shared__ double wv[LU_THREADS / 64];
+    __shared__ int wr[LU_THREADS / 64];
     __shared__ int spiv[LU_NB];
     TF* a = A + (size_t)blockIdx.x * n * n;
     int* pv = piv + (size_t)blockIdx.x * n;
@@ -187,18 +206,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                 const double v = fabs(P[j * n + r]);
                 if (v > best) { best = v; bi = r; }
             }
-            rv[t] = best;
-            ri[t] = bi;
-            __syncthreads();
-            for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
-                if (t < s) {
-                    const double v2 = rv[t + s];
-                    const int i2 = ri[t + s];
-                    if (v2 > rv[t] || (v2 == rv[t] && i2 < ri[t])) { rv[t] = v2; ri[t] = i2; }
-                }
-                __syncthreads();
-            }
-            int p = ri[0];
+            int p = block_argmax(best, bi, wv, wr);
             if (p < j || p >= m) p = j;
             if (t == 0) {
                 spiv[j] = p;
@@ -223,25 +231,26 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
             const int c = idx / m, r = idx % m;
             a[(size_t)(k0 + c) * n + k0 + r] = (TF)P[c * n + r];
         }
-        // row exchanges of this panel applied to the columns left and right of it
-        for (int j = 0; j < kb; ++j) {
-            const int p = spiv[j];
-            if (p != j)
-                for (int c = t; c < n; c += LU_THREADS) {
-                    if (c >= k0 && c < k0 + kb) continue;
-                    const TF x = a[(size_t)c * n + k0 + j];
-                    a[(size_t)c * n + k0 + j] = a[(size_t)c * n + k0 + p];
-                    a[(size_t)c * n + k0 + p] = x;
-                }
-            __syncthreads();
-        }
+        // every other column, one thread each: the panel's row exchanges in
+        // order; a trailing column then gives its U12 = L11^-1 A12 entries
+        // (registers, staged in LDS for the update)
         const int n2 = n - k0 - kb;
-        if (n2 <= 0) break;
-        // U12 = L11^-1 A12, one column per thread, staged in LDS
-        for (int c = t; c < n2; c += LU_THREADS) {
+        for (int c = t; c < n; c += LU_THREADS) {
+            if (c >= k0 && c < k0 + kb) continue;
+            TF* col = a + (size_t)c * n;
+            for (int j = 0; j < kb; ++j) {
+                const int p = spiv[j];
+                if (p != j) {
+                    const TF x = col[k0 + j];
+                    col[k0 + j] = col[k0 + p];
+                    col[k0 + p] = x;
+                }
+            }
+            if (c < k0 + kb) continue;
+            const int cc = c - k0 - kb;
             double x[LU_NB];
 #pragma unroll
-            for (int i = 0; i < LU_NB; ++i) x[i] = (i < kb) ? (double)a[(size_t)(k0 + kb + c) * n + k0 + i] : 0.0;
+            for (int i = 0; i < LU_NB; ++i) x[i] = (i < kb) ? (double)col[k0 + i] : 0.0;
 #pragma unroll
             for (int i = 1; i < LU_NB; ++i)
 #pragma unroll
@@ -250,11 +259,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
 #pragma unroll
             for (int i = 0; i < LU_NB; ++i)
                 if (i < kb) {
-                    a[(size_t)(k0 + kb + c) * n + k0 + i] = (TF)x[i];
-                    U[i * n + c] = x[i];
+                    col[k0 + i] = (TF)x[i];
+                    U[i * n + cc] = x[i];
                 }
         }
         __syncthreads();
+        if (n2 <= 0) break;
         // A22 -= L21 U12 with 4x4 tiles
         const int tr = (n2 + 3) / 4;
         const int ntile = tr * tr;

@@ -141,6 +141,75 @@ __device__ __forceinline__ void flux_v_acc(const T u[5], const TG G[5][3], const
     }
 }
 
+// Normal component of the viscous flux: Fn[a] -= s * sum_j F_v(u, G)[a][j] n[j]
+// (the same stress and heat flux as flux_v_acc, projected on n).
+template <class T, class TG>
+__device__ __forceinline__ void flux_v_n_acc(const T u[5], const TG G[5][3], const Gas& g, double s,
+                                             const double n[3], T Fn[5]) {
+    T ir = 1.0 / u[0];
+    T v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    T E = u[4] * ir;
+    T gv[3][3];
+    T gE[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) gv[i][j] = (G[1 + i][j] - v[i] * G[0][j]) * ir;
+        gE[j] = (G[4][j] - E * G[0][j]) * ir;
+    }
+    const double mu = g.mu;
+    const double kq = g.gamma * g.mu / g.Pr;
+    T dd = (2.0 / 3.0) * mu * (gv[0][0] + gv[1][1] + gv[2][2]);
+    T wn = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // (tau n)_i = mu sum_j (gv_ij + gv_ji) n_j - dd n_i
+        T tn = -dd * n[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) tn = tn + mu * (gv[i][j] + gv[j][i]) * n[j];
+        Fn[1 + i] = Fn[1 + i] - s * tn;
+        wn = wn + tn * v[i];
+    }
+    // (-q).n = kq sum_j (gE_j - v . gv_:j) n_j
+    T qn = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qn = qn + (gE[j] - (v[0] * gv[0][j] + v[1] * gv[1][j] + v[2] * gv[2][j])) * n[j];
+    Fn[4] = Fn[4] - s * (wn + kq * qn);
+}
+
+// Viscous flux of a rank-one gradient G[a][j] = du[a] n[j] (the BR2 jump
+// term): with a_i = (du_{1+i} - v_i du_0)/rho and b = (du_4 - E du_0)/rho the
+// velocity gradient is a (x) n and the energy gradient b n, so
+// tau = mu (a (x) n + n (x) a) - 2/3 mu (a.n) I and -q = kq (b - v.a) n.
+// Accumulates s * F_v into F (all 3 columns) and returns nothing else.
+template <class T>
+__device__ __forceinline__ void flux_v_rank1_acc(const T u[5], const T du[5], const double n[3], const Gas& g,
+                                                 double s, T F[5][3]) {
+    T ir = 1.0 / u[0];
+    T v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    T E = u[4] * ir;
+    T av[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) av[i] = (du[1 + i] - v[i] * du[0]) * ir;
+    T b = (du[4] - E * du[0]) * ir;
+    const double mu = g.mu;
+    const double kq = g.gamma * g.mu / g.Pr;
+    T an = av[0] * n[0] + av[1] * n[1] + av[2] * n[2];
+    T va = v[0] * av[0] + v[1] * av[1] + v[2] * av[2];
+    T vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    T dd = (2.0 / 3.0) * mu * an;
+    T mqs = kq * (b - va);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        // tau_ij = mu (a_i n_j + n_i a_j) - dd delta_ij;  (tau v)_j = mu (n_j (a.v) + a_j (n.v)) - dd v_j
+        F[1][j] = F[1][j] - s * (mu * (av[0] * n[j] + n[0] * av[j]) - ((j == 0) ? dd : T(0.0)));
+        F[2][j] = F[2][j] - s * (mu * (av[1] * n[j] + n[1] * av[j]) - ((j == 1) ? dd : T(0.0)));
+        F[3][j] = F[3][j] - s * (mu * (av[2] * n[j] + n[2] * av[j]) - ((j == 2) ? dd : T(0.0)));
+        T w = mu * (n[j] * va + av[j] * vn) - dd * v[j] + mqs * n[j];
+        F[4][j] = F[4][j] - s * w;
+    }
+}
+
 // Roe flux through unit normal n from the + (L) side to the - (R) side:
 // F = (F(uL) + F(uR)).n / 2 - |A(roe avg)| (uR - uL) / 2, waves written
 // out (acoustic vn -/+ c, entropy, two shear), no entropy fix.

@@ -73,6 +73,11 @@ void build_tables(Tab tabs[MAXP + 1], short perm[PERM_TOTAL]) {
                 for (int m = 0; m < n; ++m)
                     if (m != q) l *= (x - t.z[m]) / (t.z[q] - t.z[m]);
                 t.lag[s][q] = l;
+                // its derivative at the end: l_q'(x) = l_q(x) sum_{m != q} 1 / (x - z_m)
+                double sd = 0.0;
+                for (int m = 0; m < n; ++m)
+                    if (m != q) sd += 1.0 / (x - t.z[m]);
+                t.lagd[s][q] = l * sd;
             }
             // BR2 line weights: (sum_i L_i(x) L_i(z_q))^2 w_q
             for (int q = 0; q < n; ++q) {

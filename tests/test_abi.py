@@ -58,3 +58,24 @@ def test_enums_match_header():
         assert binding.KERNEL_KINDS[i] == name.lower()
     prec = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"DG_(FP64|FP32|BF16)\s*=\s*(\d+)", src))
     assert prec == {"FP64": binding.DG_FP64, "FP32": binding.DG_FP32, "BF16": binding.DG_BF16}
+
+
+@pytest.mark.parametrize("cname,pyname", [("pmg_opts", "PmgOpts"), ("fgmres_opts", "FgmresOpts"),
+                                          ("fgmres_stats", "FgmresStats"), ("dg_step_stats", "StepStats")])
+def test_option_structs_match_header(cname, pyname):
+    """The ctypes mirrors list the header's struct members in order."""
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    m = re.search(r"typedef struct \{([^}]*)\}\s*" + cname + r"\s*;", src)
+    assert m, cname
+    names = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        first = decl.split(",")
+        head = re.match(r"^(?:const\s+)?[A-Za-z_]\w*(?:\s*\*)*\s+(.*)$", first[0]).group(1)
+        for part in [head] + first[1:]:
+            names.append(re.sub(r"\[.*\]", "", part).strip().lstrip("*").strip())
+    fields = [f[0] for f in getattr(binding, pyname)._fields_]
+    assert fields == names

@@ -137,15 +137,17 @@ def test_bdf2_step_pmg_matches_oracle(fp32, tgv_oracle):
     assert _rel(W1.cpu().numpy().reshape(Wo.shape), W1o) < 1e-10
 
 
-def test_vcycle_graph_replays_match_eager():
+@pytest.mark.parametrize("cmf", [1, 2])
+def test_vcycle_graph_replays_match_eager(cmf):
     """pmg_apply replays a captured HIP graph; every replay, with other eager
     work and synchronisations in between, equals the eager V-cycle bitwise
-    (all kernels, reductions included, are deterministic)."""
+    (all kernels, reductions included, are deterministic).  cmf = 2: the
+    assembled coarsest level runs on the folded operator K D^-1."""
     ctx, _ = _case((2, 3, 2), 2, 0.02, True)
     W = _dev(inputs.random_state(ctx.ne, 2, seed=51))
     r1 = _dev(inputs.random_vector(ctx.ne, 2, seed=52))
     r2 = _dev(inputs.random_vector(ctx.ne, 2, seed=53))
-    ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12))
+    ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12, coarse_matrix_free=cmf))
     ctx.use_graphs(False)
     z1 = ctx.pmg_apply(r1).clone()
     z2 = ctx.pmg_apply(r2).clone()
@@ -198,6 +200,26 @@ def test_pmg_assembled_coarse_vcycle(prec):
     z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
     zo = olin.PMG(D, W, a, [2, 1], coarse_iters=10, coarse_op="exact").apply(r)
     assert _rel(z, zo) < (1e-2 if prec == "bf16" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_folded_coarsest_equals_plain(prec):
+    """The coarsest GMRES(BJ) on the stored K D^-1 (unit diagonal, face blocks
+    times the neighbour's block inverse) produces the iterate of the plain
+    right-preconditioned GMRES(BJ): FP64 to rounding (1e-9 after 12 steps);
+    BF16 storage rounds K D^-1 instead of K (within 1e-2)."""
+    ctx, _ = _case((3, 2, 2), 2, 0.02, True)
+    W = _dev(inputs.random_state(ctx.ne, 2, seed=65))
+    r = _dev(inputs.random_vector(ctx.ne, 2, seed=66))
+    pc = binding.DG_BF16 if prec == "bf16" else binding.DG_FP64
+    out = []
+    for plain in (1, 0):
+        ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12, prec_coarse=pc, coarse_matrix_free=2,
+                                                coarsest_plain=plain))
+        out.append(ctx.pmg_apply(r).cpu().numpy())
+    err = _rel(out[1], out[0])
+    print("folded vs plain coarsest", prec, err, flush=True)
+    assert err < (1e-2 if prec == "bf16" else 1e-9)
 
 
 def test_bdf2_step_mixed_bf16_matches_oracle(tgv_oracle):
