@@ -185,7 +185,6 @@ template <class TF>
 __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n) {
     extern __shared__ double lds[];
     double* P = lds;                      // panel, column-major with stride n: P[c*n + r], r < m
-    double* U = lds + (size_t)LU_NB * n;  // U12, LU_NB x (n - k0 - kb): U[t*n + c']
     __shared__ double wv[LU_THREADS / 64];
     __shared__ int wr[LU_THREADS / 64];
     __shared__ int spiv[LU_NB];
@@ -233,7 +232,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         }
         // every other column, one thread each: the panel's row exchanges in
         // order; a trailing column then gives its U12 = L11^-1 A12 entries
-        // (registers, staged in LDS for the update)
+        // (registers, written in place; the update reads them back through the cache)
         const int n2 = n - k0 - kb;
         for (int c = t; c < n; c += LU_THREADS) {
             if (c >= k0 && c < k0 + kb) continue;
@@ -247,7 +246,6 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                 }
             }
             if (c < k0 + kb) continue;
-            const int cc = c - k0 - kb;
             double x[LU_NB];
 #pragma unroll
             for (int i = 0; i < LU_NB; ++i) x[i] = (i < kb) ? (double)col[k0 + i] : 0.0;
@@ -258,10 +256,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                     if (i < kb) x[i] -= P[q * n + i] * x[q];
 #pragma unroll
             for (int i = 0; i < LU_NB; ++i)
-                if (i < kb) {
-                    col[k0 + i] = (TF)x[i];
-                    U[i * n + cc] = x[i];
-                }
+                if (i < kb) col[k0 + i] = (TF)x[i];
         }
         __syncthreads();
         if (n2 <= 0) break;
@@ -275,12 +270,15 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+            const TF* ucol[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) ucol[jj] = a + (size_t)(k0 + kb + min(c0 + jj, n2 - 1)) * n + k0;
             for (int q = 0; q < kb; ++q) {
                 double lv[4], uv[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < n2) ? P[q * n + kb + r0 + i] : 0.0;
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? U[q * n + c0 + jj] : 0.0;
+                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? (double)ucol[jj][q] : 0.0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -324,12 +322,14 @@ __global__ void __launch_bounds__(256) lu_pos_kernel(const int* __restrict__ piv
 // preloads its triangle row), the rows beyond it are updated by all lanes
 // (coalesced reads of the factor columns).  With one wavefront per block all
 // element blocks of a CU are resident together, so the sequential panel chain
-// of one block overlaps with the factor streams of the others.
+// of one block overlaps with the factor streams of the others.  At most 128
+// registers (four wavefronts per SIMD): 16 blocks per CU, e.g. a 16^3 mesh on
+// 256 CUs, run in a single round.
 constexpr int TS = 32;
 constexpr int SOLVE_THREADS = 64;
 
 template <class TF>
-__global__ void __launch_bounds__(SOLVE_THREADS)
+__global__ void __launch_bounds__(SOLVE_THREADS, 4)
     lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
                             double* __restrict__ z, int n) {
     extern __shared__ double x[];
@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS)
     for (int i = t; i < n; i += SOLVE_THREADS) zb[i] = x[i];
 }
 
-size_t lu_blocked_lds(int n) { return (size_t)2 * LU_NB * n * sizeof(double); }
+size_t lu_blocked_lds(int n) { return (size_t)LU_NB * n * sizeof(double); }
 
 template <class TF>
 hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s) {
