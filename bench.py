@@ -158,9 +158,17 @@ def run(args):
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         d = (W32 - W64).norm().item() / W64.norm().item()
+        # per-family kernel time of one instrumented mixed step (same stream, eager)
+        ctx.timing(True)
+        steps(popts32, 1, W0)
+        k32 = ctx.timing_read()
+        ctx.timing(False)
+        fams32 = {kind: dict(ms_total=ms, launches=cnt, ms_avg=ms / cnt,
+                             gbs=(by / (ms * 1e-3) / 1e9) if (by and ms > 0) else None)
+                  for kind, (ms, cnt, by, fl) in k32.items() if cnt}
         mixed = dict(time_step_s=(t3 - t2) / args.steps, rel_diff_vs_fp64=d,
                      linear_iters=[s_.linear_iters for s_ in st32], newton=[s_.newton for s_ in st32],
-                     max_rel_res_true=max(s_.max_rel_res_true for s_ in st32))
+                     max_rel_res_true=max(s_.max_rel_res_true for s_ in st32), kernels=fams32)
 
     # ---- batching (96 independent cases) and serving (Poisson request stream) ----------
     batch = None
@@ -282,8 +290,8 @@ def kernel_name(family, p, popts):
         return "lu_solve_blocked_kernel<double>" if 5 * (p + 1) ** 3 > 135 else "inv_gemv_kernel<double>"
     return {"residual": "dg_kernel<P,NS,CURVED,0>", "jvp_fd": "dg_kernel<P,NS,CURVED,1>",
             "jvp_exact": "dg_kernel<P,NS,CURVED,2>", "diag_blocks": "diag_kernel", "lu": "lu_blocked_kernel<double>",
-            "bsr": "bsr7_kernel<double,double>", "bj_coarse": "inv_gemv_kernel<double>",
-            "arnoldi": "gs_dots_kernel + gs_update_kernel + sum_stage2 + gs_finish_givens_kernel"}.get(family, family)
+            "bsr": "bsr_rows_kernel<double,double,UNIT,DOTS>", "bj_coarse": "inv_gemv_kernel<double>",
+            "arnoldi": "gs_update_kernel + gs_normalise_kernel (+ gs_dots_kernel)"}.get(family, family)
 
 
 def measured_traffic(kname, workload):

@@ -1725,10 +1725,9 @@ __global__ void __launch_bounds__(256) nbr_trace_kernel(MeshDev m, const double*
 template <int P>
 struct SzD {
     static constexpr int N = P + 1, NQ = N * N * N, NF = N * N;
-    static constexpr int OFF_U = 20 * NQ;                 // [0, 20NQ): interpolation buffers, later test A/B
+    static constexpr int OFF_U = 20 * NQ;                 // [0, 20NQ): interpolation | face tangents of a round | test A/B
     static constexpr int OFF_G = OFF_U + 5 * NQ;          // Gauss values (5NQ), reference gradients (15NQ)
-    static constexpr int OFF_F = OFF_G + 15 * NQ;         // face integrand tangents (120 NF)
-    static constexpr int OFF_H = OFF_F + 120 * NF;        // test-back sweeps (15 NQ)
+    static constexpr int OFF_H = OFF_G + 15 * NQ;         // test-back sweeps (15 NQ)
     static constexpr int TOT = OFF_H + 15 * NQ;
 };
 template <int P> struct LaunchD { static constexpr int EPB = (P == 1) ? 8 : ((P == 2) ? 2 : 1); };
@@ -1834,9 +1833,11 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
         }
     }
     __syncthreads();
-    double* sF = S + S_::OFF_F;
-    if (active) {
-        for (int fp = q; fp < 6 * NF; fp += NQ) {
+    // rounds of NQ face points (N whole faces), tangents in [0, 20 NQ), spread per round
+    double* sF = S;
+    for (int r = 0; r * NQ < 6 * NF; ++r) {
+        const int fp = r * NQ + q;
+        if (active && fp < 6 * NF) {
             const int f = fp / NF, fq = fp % NF;
             const int d = f >> 1, s = f & 1;
             const int t1 = (d == 0) ? 1 : 0;
@@ -1908,30 +1909,32 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
             Dual fo[20];
             face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
                                      fo);
-            double* so = sF + (f * NF + fq) * 20;
+            double* so = sF + q * 20;
 #pragma unroll
             for (int k = 0; k < 20; ++k) so[k] = fo[k].d;
         }
-    }
-    __syncthreads();
-    if (active) {
+        __syncthreads();
+        if (active) {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int d = f >> 1, s = f & 1;
-            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-            const double l = tb.lag[s][ii[d]];
-            const double* fo = sF + (f * NF + ii[t1] * N + ii[t2]) * 20;
+            for (int fl = 0; fl < N; ++fl) {
+                const int f = r * N + fl;
+                if (f >= 6) break;
+                const int d = f >> 1, s = f & 1;
+                const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+                const double l = tb.lag[s][ii[d]];
+                const double* fo = sF + (fl * NF + ii[t1] * N + ii[t2]) * 20;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                Bd[a] = fma(l, fo[a], Bd[a]);
-                if constexpr (NS) {
+                for (int a = 0; a < 5; ++a) {
+                    Bd[a] = fma(l, fo[a], Bd[a]);
+                    if constexpr (NS) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) Ad[a][k] = fma(l, fo[5 + a * 3 + k], Ad[a][k]);
+                        for (int k = 0; k < 3; ++k) Ad[a][k] = fma(l, fo[5 + a * 3 + k], Ad[a][k]);
+                    }
                 }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     double* sA = S;
     double* sB = S + 15 * NQ;
     double* H = S + S_::OFF_H;
