@@ -213,8 +213,7 @@ void jvp_fd(dg_ctx* ctx, const double* W, const double* RW, const double* v, dou
         dot(ctx, W, W, ctx->N, sc(ctx, S_NW2));
         nw2 = sc(ctx, S_NW2);
     }
-    dot(ctx, v, v, ctx->N, sc(ctx, S_NV2));
-    CK(launch_fd_step(nw2, sc(ctx, S_NV2), 1e-7, sc(ctx, S_H), ctx->s));
+    CK(launch_fd_step_of(v, ctx->N, nw2, 1e-7, ctx->partial.p, sc(ctx, S_NV2), sc(ctx, S_H), ctx->s));
     timed(ctx, DG_K_JVP_FD, 32.0 * (double)ctx->N, 0.0, [&] { return launch_jvp_fd(ctx->a, W, RW, v, sc(ctx, S_H), shift, y, ctx->s); });
 }
 

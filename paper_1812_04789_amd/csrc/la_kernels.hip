@@ -68,6 +68,29 @@ hipError_t launch_dot(const double* x, const double* y, size_t n, double* partia
     return launch_multi_dot(x, n, 1, y, n, partial, out, s);
 }
 
+// ||v||^2 from the first-stage partials (the same second stage as sum_stage2),
+// then the FD step h = eps sqrt(1 + ||W||) / ||v|| (0 for v = 0): one block.
+__global__ void __launch_bounds__(RED_THREADS) fd_step_stage2(const double* __restrict__ partial, int nparts,
+                                                              const double* __restrict__ nw2, double eps,
+                                                              double* __restrict__ nv2, double* __restrict__ h) {
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
+    const double s2 = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        nv2[0] = s2;
+        const double nv = sqrt(s2);
+        h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2[0])) / nv : 0.0;
+    }
+}
+hipError_t launch_fd_step_of(const double* v, size_t n, const double* nw2, double eps, double* partial, double* nv2,
+                             double* h, hipStream_t s) {
+    const int nbk = red_blocks(n);
+    hipLaunchKernelGGL(multi_dot_stage1, dim3(nbk), dim3(RED_THREADS), 0, s, v, n, 0, 1, v, n, partial);
+    hipLaunchKernelGGL(fd_step_stage2, dim3(1), dim3(RED_THREADS), 0, s, partial, nbk, nw2, eps, nv2, h);
+    return hipGetLastError();
+}
+
 __global__ void fd_step_kernel(const double* nw2, const double* nv2, double eps, double* h) {
     const double nv = sqrt(nv2[0]);
     h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2[0])) / nv : 0.0;

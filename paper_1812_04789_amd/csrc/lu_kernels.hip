@@ -153,73 +153,77 @@ template hipError_t launch_extract_sub<double>(const double*, int, int, int, dou
 template hipError_t launch_extract_sub<float>(const double*, int, int, int, float*, int, hipStream_t);
 
 // ---- blocked variants used by the smoother -------------------------------------------------
-// Right-looking PLU with LU_NB-column panels.  The panel (rows k0..n-1) is
-// factored in LDS (pivot search, row exchange, scaling, rank-1 updates), the
-// panel's row exchanges are applied to the other columns, U12 = L11^-1 A12 is
-// solved per column in registers and staged in LDS, and the trailing matrix
-// A22 -= L21 U12 is updated with 4x4 register tiles.  Pivots are the same
-// partial-pivoting choices as the unblocked kernel (max |a_ik|, lowest index on
-// ties); only the summation order of the trailing updates differs.
-constexpr int LU_NB = 16;
+// Right-looking PLU with column panels.  The panel (rows k0..n-1) is factored
+// in LDS (pivot search, row exchange, scaling, rank-1 updates); every other
+// column then takes the panel's row exchanges and, right of the panel, its
+// U12 = L11^-1 A12 entries; the trailing matrix A22 -= L21 U12 is updated
+// with 4x4 register tiles.  Pivots are the partial-pivoting choices of the
+// unblocked kernel (max |a_ik|, lowest index on ties); only the summation
+// order of the trailing updates differs.
 
 // Largest |value| with the lowest row index on ties, over the block: a
 // butterfly inside each wavefront, then the wavefront winners in order.
-__device__ __forceinline__ int block_argmax(double v, int r, double* sv, int* sr) {
+template <class TA>
+__device__ __forceinline__ int block_argmax(TA v, int r, TA* sv, int* sr) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        const double v2 = __shfl_xor(v, o, 64);
+        const TA v2 = __shfl_xor(v, o, 64);
         const int r2 = __shfl_xor(r, o, 64);
         if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
     }
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if ((threadIdx.x & 63) == 0) { sv[w] = v; sr[w] = r; }
     __syncthreads();
-    double bv = sv[0];
+    TA bv = sv[0];
     int br = sr[0];
     for (int i = 1; i < nw; ++i)
         if (sv[i] > bv || (sv[i] == bv && sr[i] < br)) { bv = sv[i]; br = sr[i]; }
     return br;
 }
 
-template <class TF>
+// TF: storage type of the blocks; TA: arithmetic of the factorisation (the
+// panel in LDS and every update); NBW: panel width.  FP64 blocks: double,
+// 16 columns; FP32 blocks: float arithmetic, 32 columns (the same 40 KB panel,
+// half the trailing-matrix passes).
+template <class TF, class TA, int NBW>
 __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n) {
-    extern __shared__ double lds[];
-    double* P = lds;                      // panel, column-major with stride n: P[c*n + r], r < m
-    __shared__ double wv[LU_THREADS / 64];
+    extern __shared__ double lds_raw[];
+    TA* P = reinterpret_cast<TA*>(lds_raw);  // panel, column-major with stride n: P[c*n + r], r < m
+    __shared__ TA wv[LU_THREADS / 64];
     __shared__ int wr[LU_THREADS / 64];
-    __shared__ int spiv[LU_NB];
+    __shared__ int spiv[NBW];
     TF* a = A + (size_t)blockIdx.x * n * n;
     int* pv = piv + (size_t)blockIdx.x * n;
     const int t = threadIdx.x;
-    for (int k0 = 0; k0 < n; k0 += LU_NB) {
-        const int kb = min(LU_NB, n - k0), m = n - k0;
+    for (int k0 = 0; k0 < n; k0 += NBW) {
+        const int kb = min(NBW, n - k0), m = n - k0;
         for (int idx = t; idx < m * kb; idx += LU_THREADS) {
             const int c = idx / m, r = idx % m;
-            P[c * n + r] = (double)a[(size_t)(k0 + c) * n + k0 + r];
+            P[c * n + r] = (TA)a[(size_t)(k0 + c) * n + k0 + r];
         }
         __syncthreads();
         for (int j = 0; j < kb; ++j) {
-            double best = -1.0;
+            TA best = -1;
             int bi = m;
             for (int r = j + t; r < m; r += LU_THREADS) {
-                const double v = fabs(P[j * n + r]);
+                const TA v = fabs(P[j * n + r]);
                 if (v > best) { best = v; bi = r; }
             }
-            int p = block_argmax(best, bi, wv, wr);
+            int p = block_argmax<TA>(best, bi, wv, wr);
             if (p < j || p >= m) p = j;
             if (t == 0) {
                 spiv[j] = p;
                 pv[k0 + j] = k0 + p;
             }
             if (p != j && t < kb) {
-                const double x = P[t * n + j];
+                const TA x = P[t * n + j];
                 P[t * n + j] = P[t * n + p];
                 P[t * n + p] = x;
             }
             __syncthreads();
-            const double inv = 1.0 / P[j * n + j];
+            const TA inv = TA(1) / P[j * n + j];
             for (int r = j + 1 + t; r < m; r += LU_THREADS) {
-                const double l = P[j * n + r] * inv;
+                const TA l = P[j * n + r] * inv;
                 P[j * n + r] = l;
                 for (int c = j + 1; c < kb; ++c) P[c * n + r] -= l * P[c * n + j];
             }
@@ -246,16 +250,16 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                 }
             }
             if (c < k0 + kb) continue;
-            double x[LU_NB];
+            TA x[NBW];
 #pragma unroll
-            for (int i = 0; i < LU_NB; ++i) x[i] = (i < kb) ? (double)col[k0 + i] : 0.0;
+            for (int i = 0; i < NBW; ++i) x[i] = (i < kb) ? (TA)col[k0 + i] : TA(0);
 #pragma unroll
-            for (int i = 1; i < LU_NB; ++i)
+            for (int i = 1; i < NBW; ++i)
 #pragma unroll
                 for (int q = 0; q < i; ++q)
                     if (i < kb) x[i] -= P[q * n + i] * x[q];
 #pragma unroll
-            for (int i = 0; i < LU_NB; ++i)
+            for (int i = 0; i < NBW; ++i)
                 if (i < kb) col[k0 + i] = (TF)x[i];
         }
         __syncthreads();
@@ -265,20 +269,20 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         const int ntile = tr * tr;
         for (int tile = t; tile < ntile; tile += LU_THREADS) {
             const int r0 = (tile % tr) * 4, c0 = (tile / tr) * 4;
-            double acc[4][4];
+            TA acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0;
             const TF* ucol[4];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) ucol[jj] = a + (size_t)(k0 + kb + min(c0 + jj, n2 - 1)) * n + k0;
             for (int q = 0; q < kb; ++q) {
-                double lv[4], uv[4];
+                TA lv[4], uv[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < n2) ? P[q * n + kb + r0 + i] : 0.0;
+                for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < n2) ? P[q * n + kb + r0 + i] : TA(0);
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? (double)ucol[jj][q] : 0.0;
+                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? (TA)ucol[jj][q] : TA(0);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -290,7 +294,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                 TF* colp = a + (size_t)(k0 + kb + c0 + jj) * n + k0 + kb + r0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (r0 + i < n2) colp[i] = (TF)((double)colp[i] - acc[i][jj]);
+                    if (r0 + i < n2) colp[i] = (TF)((TA)colp[i] - acc[i][jj]);
             }
         }
         __syncthreads();
@@ -414,16 +418,20 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
     for (int i = t; i < n; i += SOLVE_THREADS) zb[i] = x[i];
 }
 
-size_t lu_blocked_lds(int n) { return (size_t)LU_NB * n * sizeof(double); }
+template <class TF>
+struct LuCfg;
+template <> struct LuCfg<double> { using TA = double; static constexpr int NBW = 16; };
+template <> struct LuCfg<float> { using TA = float; static constexpr int NBW = 32; };
 
 template <class TF>
 hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
-    const size_t lds = lu_blocked_lds(n);
-    hipError_t e = hipFuncSetAttribute((const void*)lu_blocked_kernel<TF>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    using C = LuCfg<TF>;
+    const size_t lds = (size_t)C::NBW * n * sizeof(typename C::TA);
+    auto kern = lu_blocked_kernel<TF, typename C::TA, C::NBW>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lu_blocked_kernel<TF>, dim3(nblk), dim3(LU_THREADS), lds, s, A, piv, n);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(LU_THREADS), lds, s, A, piv, n);
     e = hipGetLastError();
     if (e != hipSuccess || !pos) return e;
     hipLaunchKernelGGL(lu_pos_kernel, dim3(nblk), dim3(256), n * sizeof(int), s, piv, pos, n);
