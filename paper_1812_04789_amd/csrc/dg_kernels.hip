@@ -1572,9 +1572,18 @@ __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const
         const AT* xe = xs + (size_t)(e - e_first) * NBLK * ldr;
         const int nk = NBLK * ldr / W;
         const SF* base = A + ((g / 64) * (size_t)nk * 64 + (g % 64)) * W;
-        AT acc = 0;
-        for (int kc = 0; kc < nk; ++kc) bsr_chunk<SF, AT>(base + (size_t)kc * 64 * W, xe + kc * W, acc);
-        yg = UNIT ? x[g] + (double)acc : (double)acc;
+        // four independent accumulators over interleaved chunks (loads of an
+        // unrolled group in flight together), added in a fixed order
+        AT acc[4] = {0, 0, 0, 0};
+        int kc = 0;
+        for (; kc + 4 <= nk; kc += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                bsr_chunk<SF, AT>(base + (size_t)(kc + u) * 64 * W, xe + (kc + u) * W, acc[u]);
+        }
+        for (; kc < nk; ++kc) bsr_chunk<SF, AT>(base + (size_t)kc * 64 * W, xe + kc * W, acc[0]);
+        const AT sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        yg = UNIT ? x[g] + (double)sum : (double)sum;
         y[g] = yg;
     }
     if constexpr (DOTS) {

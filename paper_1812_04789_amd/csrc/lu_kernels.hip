@@ -1,8 +1,9 @@
 // Element block-Jacobi (Sec. 6.3): batched PLU with partial pivoting of the
-// element diagonal blocks and the block solves z = D^-1 r used by the
-// smoother.  Blocks are column-major (a[col*n + row]); one workgroup per
-// block.  Factor storage type TF is double or float (vectors stay FP64 and
-// the solve arithmetic is FP64).
+// element diagonal blocks, the simple per-block solve of the library's
+// batched-LU entry point, coarse sub-block extraction and the explicit block
+// inverse.  Blocks are column-major (a[col*n + row]); one workgroup per
+// block.  Factor storage type TF is double or float.  The smoother's apply
+// kernels are in bj_apply.hip.
 #include "internal.h"
 
 namespace dg {
@@ -321,103 +322,6 @@ __global__ void __launch_bounds__(256) lu_pos_kernel(const int* __restrict__ piv
     for (int i = threadIdx.x; i < n; i += blockDim.x) po[i] = sp[i];
 }
 
-// z = U^-1 L^-1 P r with TS-wide panels, one wavefront per element block:
-// the TS x TS diagonal triangle is solved with cross-lane shuffles (each lane
-// preloads its triangle row), the rows beyond it are updated by all lanes
-// (coalesced reads of the factor columns).  With one wavefront per block all
-// element blocks of a CU are resident together, so the sequential panel chain
-// of one block overlaps with the factor streams of the others.  At most 128
-// registers (four wavefronts per SIMD): 16 blocks per CU, e.g. a 16^3 mesh on
-// 256 CUs, run in a single round.
-constexpr int TS = 32;
-constexpr int SOLVE_THREADS = 64;
-
-template <class TF>
-__global__ void __launch_bounds__(SOLVE_THREADS, 4)
-    lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
-                            double* __restrict__ z, int n) {
-    extern __shared__ double x[];
-    const TF* a = LU + (size_t)blockIdx.x * n * n;
-    const int* po = pos + (size_t)blockIdx.x * n;
-    const double* rb = r + (size_t)blockIdx.x * n;
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    for (int i = t; i < n; i += SOLVE_THREADS) x[i] = rb[po[i]];
-    __syncthreads();
-    // forward, unit lower
-    for (int k0 = 0; k0 < n; k0 += TS) {
-        const int kb = min(TS, n - k0);
-        {
-            // lane i holds row i of the diagonal triangle (loads issued together)
-            TF lrow[TS];
-            const int li = (lane < kb) ? lane : 0;
-#pragma unroll
-            for (int j = 0; j < TS; ++j) lrow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (!(j < kb && lane < kb && lane > j)) lrow[j] = TF(0);
-            double xi = (lane < kb) ? x[k0 + lane] : 0.0;
-#pragma unroll
-            for (int j = 0; j < TS - 1; ++j) {
-                const double xj = __shfl(xi, j, 64);
-                xi -= (double)lrow[j] * xj;
-            }
-            if (lane < kb) x[k0 + lane] = xi;
-        }
-        __syncthreads();
-        for (int row = k0 + kb + t; row < n; row += SOLVE_THREADS) {
-            // the panel's factor entries of this row, all loads in flight at once
-            TF av[TS];
-#pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
-            double acc = x[row];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (j < kb) acc -= (double)av[j] * x[k0 + j];
-            x[row] = acc;
-        }
-        __syncthreads();
-    }
-    // backward, upper
-    const int nb0 = ((n - 1) / TS) * TS;
-    for (int k0 = nb0; k0 >= 0; k0 -= TS) {
-        const int kb = min(TS, n - k0);
-        {
-            TF urow[TS];
-            const int ui = (lane < kb) ? lane : 0;
-#pragma unroll
-            for (int j = 0; j < TS; ++j) urow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (!(j < kb && lane < kb && lane <= j)) urow[j] = TF(0);
-            double xi = (lane < kb) ? x[k0 + lane] : 0.0;
-#pragma unroll
-            for (int j = TS - 1; j >= 0; --j) {
-                if (j < kb) {
-                    if (lane == j) xi /= (double)urow[j];
-                    const double xj = __shfl(xi, j, 64);
-                    if (lane < j) xi -= (double)urow[j] * xj;
-                }
-            }
-            if (lane < kb) x[k0 + lane] = xi;
-        }
-        __syncthreads();
-        for (int row = t; row < k0; row += SOLVE_THREADS) {
-            TF av[TS];
-#pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
-            double acc = x[row];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (j < kb) acc -= (double)av[j] * x[k0 + j];
-            x[row] = acc;
-        }
-        __syncthreads();
-    }
-    double* zb = z + (size_t)blockIdx.x * n;
-    for (int i = t; i < n; i += SOLVE_THREADS) zb[i] = x[i];
-}
-
 template <class TF>
 struct LuCfg;
 template <> struct LuCfg<double> { using TA = double; static constexpr int NBW = 16; };
@@ -439,19 +343,6 @@ hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStre
 }
 template hipError_t launch_lu_blocked<double>(double*, int*, int*, int, int, hipStream_t);
 template hipError_t launch_lu_blocked<float>(float*, int*, int*, int, int, hipStream_t);
-
-template <class TF>
-hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
-                                   hipStream_t s) {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(lu_solve_blocked_kernel<TF>, dim3(nblk), dim3(SOLVE_THREADS), n * sizeof(double), s, LU, pos,
-                       r, z, n);
-    return hipGetLastError();
-}
-template hipError_t launch_lu_solve_blocked<double>(const double*, const int*, const double*, double*, int, int,
-                                                    hipStream_t);
-template hipError_t launch_lu_solve_blocked<float>(const float*, const int*, const double*, double*, int, int,
-                                                   hipStream_t);
 
 // ---- explicit block inverse for the smoother apply --------------------------------------------
 // X = A^-1 from the PLU factors: X starts as P I (X[c][i] = 1 iff pos[i] = c)
@@ -614,65 +505,5 @@ hipError_t launch_lu_inverse(const TF* LU, const int* pos, double* Xw, TF* Xout,
 }
 template hipError_t launch_lu_inverse<double>(const double*, const int*, double*, double*, int, int, hipStream_t);
 template hipError_t launch_lu_inverse<float>(const float*, const int*, double*, float*, int, int, hipStream_t);
-
-// z = X r per block with the explicit inverse (column-major, storage TF).
-// Four wavefronts per block, wavefront w takes columns c = w (mod 4) two at a
-// time; lane i accumulates rows i, i+64, ... (every column read is a
-// contiguous run of rows); the four partial sums are added in a fixed order.
-// FP64 accumulation.
-constexpr int GEMV_THREADS = 256;
-constexpr int GEMV_ROWS = 5;     // rows per lane (n <= 320)
-
-template <class TF>
-__global__ void __launch_bounds__(GEMV_THREADS)
-    inv_gemv_kernel(const TF* __restrict__ X, const double* __restrict__ r, double* __restrict__ z, int n) {
-    extern __shared__ double rs[];             // n entries of r, then 4 x n partial sums
-    double* part = rs + n;
-    const TF* xb = X + (size_t)blockIdx.x * n * n;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int i = t; i < n; i += GEMV_THREADS) rs[i] = r[(size_t)blockIdx.x * n + i];
-    __syncthreads();
-    double acc[GEMV_ROWS];
-#pragma unroll
-    for (int k = 0; k < GEMV_ROWS; ++k) acc[k] = 0.0;
-    int c = w;
-    for (; c + 4 < n; c += 8) {
-        const double r0 = rs[c], r1 = rs[c + 4];
-        const TF* c0 = xb + (size_t)c * n;
-        const TF* c1 = xb + (size_t)(c + 4) * n;
-#pragma unroll
-        for (int k = 0; k < GEMV_ROWS; ++k) {
-            const int i = lane + k * 64;
-            if (i < n) acc[k] = fma((double)c1[i], r1, fma((double)c0[i], r0, acc[k]));
-        }
-    }
-    for (; c < n; c += 4) {
-        const double r0 = rs[c];
-        const TF* c0 = xb + (size_t)c * n;
-#pragma unroll
-        for (int k = 0; k < GEMV_ROWS; ++k) {
-            const int i = lane + k * 64;
-            if (i < n) acc[k] = fma((double)c0[i], r0, acc[k]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < GEMV_ROWS; ++k) {
-        const int i = lane + k * 64;
-        if (i < n) part[w * n + i] = acc[k];
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += GEMV_THREADS)
-        z[(size_t)blockIdx.x * n + i] = ((part[i] + part[n + i]) + part[2 * n + i]) + part[3 * n + i];
-}
-
-template <class TF>
-hipError_t launch_inv_gemv(const TF* X, const double* r, double* z, int nblk, int n, hipStream_t s) {
-    if (nblk <= 0) return hipSuccess;
-    if (n > 64 * GEMV_ROWS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(inv_gemv_kernel<TF>, dim3(nblk), dim3(GEMV_THREADS), 5 * n * sizeof(double), s, X, r, z, n);
-    return hipGetLastError();
-}
-template hipError_t launch_inv_gemv<double>(const double*, const double*, double*, int, int, hipStream_t);
-template hipError_t launch_inv_gemv<float>(const float*, const double*, double*, int, int, hipStream_t);
 
 }  // namespace dg
