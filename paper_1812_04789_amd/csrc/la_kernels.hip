@@ -357,6 +357,31 @@ __global__ void __launch_bounds__(RED_THREADS)
         if (threadIdx.x == 0) pout[blockIdx.x] = sm;
         return;
     }
+    if (k <= 2 * GS_CH) {
+        // one pass: the basis entries of a row stay in registers for the
+        // update and the dots (the same per-thread sums as the two passes)
+        double a0[GS_CH], a1[GS_CH];
+#pragma unroll
+        for (int c = 0; c < GS_CH; ++c) a0[c] = a1[c] = 0.0;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            double v[2 * GS_CH];
+#pragma unroll
+            for (int c = 0; c < 2 * GS_CH; ++c) v[c] = (c < k) ? V[(size_t)c * n + i] : 0.0;
+            double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < 2 * GS_CH; ++c)
+                if (c < k) wi -= hs[c] * v[c];
+            w[i] = wi;
+#pragma unroll
+            for (int c = 0; c < GS_CH; ++c) {
+                if (c < k) a0[c] = fma(v[c], wi, a0[c]);
+                if (GS_CH + c < k) a1[c] = fma(v[GS_CH + c], wi, a1[c]);
+            }
+        }
+        block_sum_cols<GS_CH>(a0, min(GS_CH, k), sh, pout + blockIdx.x, gridDim.x);
+        if (k > GS_CH) block_sum_cols<GS_CH>(a1, k - GS_CH, sh, pout + (size_t)GS_CH * gridDim.x + blockIdx.x, gridDim.x);
+        return;
+    }
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wi = w[i];
         for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
