@@ -249,3 +249,38 @@ def test_block_jacobi_parity_high_order(p, fp32):
     z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
     zo = olin.BlockJacobi(D, W, a).apply(r)
     assert _rel(z, zo) < (1e-4 if fp32 else 1e-10)
+
+
+def _golden_p4():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tgv_p4_curved_step.txt")
+    shape = None
+    vals = []
+    for line in open(path):
+        if line.startswith("# shape"):
+            shape = tuple(int(x.strip(";")) for x in line.split()[2:5])
+        elif not line.startswith("#"):
+            vals.append(float(line))
+    a = np.array(vals)
+    n = int(np.prod(shape))
+    return a[:n].reshape(shape), a[n:].reshape(shape)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_bdf2_step_p4_curved_matches_oracle(mixed):
+    """The low-Mach curved p = 4 workload's path (pMG 4-2-1, assembled folded
+    coarsest level; mixed: FP32 fine factors, BF16 coarse operators) on a
+    curved 2x2x1 mesh against the oracle's W^{n+1} stored by
+    tests/golden/make_tgv_p4_curved_step.py (1e-10 relative)."""
+    W0o, W1o = _golden_p4()
+    ctx, _ = _case((2, 2, 1), 4, 1.0 / 1600, True, amp=0.05)
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.01)))
+    assert _rel(Wg.cpu().numpy().reshape(W0o.shape), W0o) < 1e-13
+    popts = binding.pmg_opts([4, 2, 1], prec_fine=binding.DG_FP32 if mixed else binding.DG_FP64,
+                             prec_coarse=binding.DG_BF16 if mixed else binding.DG_FP64, coarse_matrix_free=2)
+    W1, st = ctx.bdf2_step(Wg, None, 0.05, popts, binding.fgmres_opts(restart=40, rtol=1e-8))
+    err = _rel(W1.cpu().numpy().reshape(W1o.shape), W1o)
+    print("TGV p4 curved mixed=%s: newton %d its %d rel_res %.2e err %.2e" % (mixed, st.newton, st.linear_iters,
+                                                                              st.max_rel_res_true, err), flush=True)
+    assert st.max_rel_res_true <= 1e-8
+    assert err < 1e-10
