@@ -147,6 +147,24 @@ def run(args):
         jv[name]["kernel_gbs"] = by / (jv[name]["kernel_ms"] * 1e-3) / 1e9
         jv[name]["hbm_frac"] = jv[name]["kernel_gbs"] / HBM_PEAK_GBS
 
+    # cold FD product: a 512 MB write between calls evicts the 256 MB last-level
+    # cache, so W, v, R(W) and the neighbour reads come from HBM (kernel time only)
+    flush = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    ctx.timing(True)
+    for _ in range(10):
+        flush.fill_(1.0)
+        ctx.jvp(W0, RW, v, 30.0, y)
+    torch.cuda.synchronize()
+    kk = ctx.timing_read()
+    ctx.timing(False)
+    del flush
+    kms = kk["jvp_fd"][0] / max(kk["jvp_fd"][1], 1)
+    jv["fd_cold"] = dict(kernel_ms=kms, gdof_s=ctx.ndof / (kms * 1e-3) / 1e9,
+                         kernel_gbs=32.0 * ctx.ndof / (kms * 1e-3) / 1e9,
+                         hbm_frac=32.0 * ctx.ndof / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    if args.workload == "tgv_p3_16" and not args.no_large_jvp:
+        jv["fd_32cube"] = large_jvp()
+
     # ---- mixed precision steps (FP32 fine factors, BF16 coarse operators) -------------
     mixed = None
     if not args.no_mixed and len(wl["levels"]) > 0:
@@ -212,6 +230,34 @@ def run(args):
     }
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def large_jvp():
+    """FD product on the 32^3 p=3 Taylor-Green mesh (10.5 M DOF, 335 MB per
+    product: larger than the last-level cache), kernel time over 20 calls."""
+    import torch
+    from paper_1812_04789_amd import binding, inputs
+    L = 2 * math.pi
+    c = binding.Context((32, 32, 32), (0, 0, 0), (L, L, L), 3, gamma=1.4, mu=1.0 / 1600, Pr=0.71, eta=7.0)
+    W = c.project(torch.tensor(inputs.taylor_green(c.quad_points().cpu().numpy(), mach=0.1).reshape(-1),
+                               device="cuda"))
+    v = torch.tensor(inputs.random_vector(c.ne, 3, seed=7).reshape(-1), device="cuda")
+    RW = c.residual(W)
+    y = c.empty()
+    for _ in range(3):
+        c.jvp(W, RW, v, 30.0, y)
+    c.timing(True)
+    for _ in range(20):
+        c.jvp(W, RW, v, 30.0, y)
+    torch.cuda.synchronize()
+    kk = c.timing_read()
+    c.timing(False)
+    kms = kk["jvp_fd"][0] / max(kk["jvp_fd"][1], 1)
+    out = dict(ndof=c.ndof, kernel_ms=kms, gdof_s=c.ndof / (kms * 1e-3) / 1e9,
+               kernel_gbs=32.0 * c.ndof / (kms * 1e-3) / 1e9,
+               hbm_frac=32.0 * c.ndof / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    c.close()
+    return out
 
 
 def batch_bench(args):
@@ -357,6 +403,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tgv_p3_16", choices=sorted(WORKLOADS))
     ap.add_argument("--jvp-reps", type=int, default=30)
+    ap.add_argument("--no-large-jvp", action="store_true", help="skip the 32^3 p=3 FD product")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
