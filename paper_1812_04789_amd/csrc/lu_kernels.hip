@@ -182,6 +182,48 @@ __device__ __forceinline__ int block_argmax(TA v, int r, TA* sv, int* sr) {
     return br;
 }
 
+// A22 -= L21 U12 for one panel with 16 x 16 x 4 matrix-core instructions.
+// Wavefront w of the block takes tiles w, w + 4, ...; in a tile lane l holds
+//   A operand: -L21[r0 + l%16][kk + l/16]   (from the LDS panel),
+//   B operand:  U12[kk + l/16][c0 + l%16]   (from the factored rows in memory),
+//   accumulator item i, column c0 + l%16, row r0 + l/16 + 4 i (FP64) or
+//   r0 + 4 (l/16) + i (FP32): the two instructions order their results
+//   differently across the lanes,
+// so the accumulator starts at zero and is added to the tile of A22 at the
+// end.  Out-of-range rows and columns enter as zeros and are not stored.
+template <class TF, class TA, int NBW>
+__device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const TA* P, int n, int k0, int kb, int n2,
+                                                     int t) {
+    typedef TA acc4 __attribute__((ext_vector_type(4)));
+    const int lane = t & 63, wv = t >> 6, nwv = LU_THREADS / 64;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (n2 + 15) / 16;
+    for (int tile = wv; tile < nt * nt; tile += nwv) {
+        const int r0 = (tile % nt) * 16, c0 = (tile / nt) * 16;
+        const bool rok = r0 + li < n2, cok = c0 + li < n2;
+        const TF* ucol = a + (size_t)(k0 + kb + (cok ? c0 + li : 0)) * n + k0;
+        acc4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NBW; kk += 4) {
+            const int k = kk + lk;
+            const TA av = (rok && k < kb) ? -P[k * n + kb + r0 + li] : TA(0);
+            const TA bv = (cok && k < kb) ? (TA)ucol[k] : TA(0);
+            if constexpr (sizeof(TA) == 8)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            else
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+        if (cok) {
+            TF* colp = a + (size_t)(k0 + kb + c0 + li) * n + k0 + kb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = (sizeof(TA) == 8) ? r0 + lk + 4 * i : r0 + 4 * lk + i;
+                if (r < n2) colp[r] = (TF)((TA)colp[r] + acc[i]);
+            }
+        }
+    }
+}
+
 // TF: storage type of the blocks; TA: arithmetic of the factorisation (the
 // panel in LDS and every update); NBW: panel width.  FP64 blocks: double,
 // 16 columns; FP32 blocks: float arithmetic, 32 columns (the same 40 KB panel,
@@ -265,39 +307,9 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         }
         __syncthreads();
         if (n2 <= 0) break;
-        // A22 -= L21 U12 with 4x4 tiles
-        const int tr = (n2 + 3) / 4;
-        const int ntile = tr * tr;
-        for (int tile = t; tile < ntile; tile += LU_THREADS) {
-            const int r0 = (tile % tr) * 4, c0 = (tile / tr) * 4;
-            TA acc[4][4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0;
-            const TF* ucol[4];
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) ucol[jj] = a + (size_t)(k0 + kb + min(c0 + jj, n2 - 1)) * n + k0;
-            for (int q = 0; q < kb; ++q) {
-                TA lv[4], uv[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) lv[i] = (r0 + i < n2) ? P[q * n + kb + r0 + i] : TA(0);
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) uv[jj] = (c0 + jj < n2) ? (TA)ucol[jj][q] : TA(0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(lv[i], uv[jj], acc[i][jj]);
-            }
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                if (c0 + jj >= n2) continue;
-                TF* colp = a + (size_t)(k0 + kb + c0 + jj) * n + k0 + kb + r0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (r0 + i < n2) colp[i] = (TF)((TA)colp[i] - acc[i][jj]);
-            }
-        }
+        // A22 -= L21 U12 on the matrix cores: 16 x 16 tiles of A22, one per
+        // wavefront at a time, K = 4 per instruction over the panel width
+        trailing_update_mfma<TF, TA, NBW>(a, P, n, k0, kb, n2, t);
         __syncthreads();
     }
 }
