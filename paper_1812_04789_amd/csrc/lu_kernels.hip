@@ -182,43 +182,73 @@ __device__ __forceinline__ int block_argmax(TA v, int r, TA* sv, int* sr) {
     return br;
 }
 
-// A22 -= L21 U12 for one panel with 16 x 16 x 4 matrix-core instructions.
-// Wavefront w of the block takes tiles w, w + 4, ...; in a tile lane l holds
-//   A operand: -L21[r0 + l%16][kk + l/16]   (from the LDS panel),
-//   B operand:  U12[kk + l/16][c0 + l%16]   (from the factored rows in memory),
-//   accumulator item i, column c0 + l%16, row r0 + l/16 + 4 i (FP64) or
-//   r0 + 4 (l/16) + i (FP32): the two instructions order their results
-//   differently across the lanes,
-// so the accumulator starts at zero and is added to the tile of A22 at the
-// end.  Out-of-range rows and columns enter as zeros and are not stored.
+// A22 -= L21 U12 for one panel with 16 x 16 x 4 matrix-core instructions,
+// computed as its transpose U12^T L21^T so that the lanes of a result run
+// down a column of A22 (contiguous in the column-major block).  Wavefront w
+// of the block takes the 16-column strips w, w + 4, ... of A22: the strip's
+// U12 entries stay in registers while the wavefront walks down the strip,
+// UPD_G tiles at a time (all their loads issued before the first store, so
+// the memory latency of the group overlaps).  In a tile lane l holds
+//   A operand:  U12[kk + l/16][c0 + l%16],
+//   B operand: -L21[r0 + l%16][kk + l/16]    (LDS panel),
+//   accumulator item i: row r0 + l%16 of A22, column c0 + l/16 + 4 i (FP64)
+//   or c0 + 4 (l/16) + i (FP32): the two instructions order their results
+//   differently across the lanes.
+// The accumulator starts from the A22 tile, so each entry becomes
+// a - sum_k l_k u_k accumulated in panel order.  Out-of-range rows and
+// columns enter as zeros and are not stored.
+constexpr int UPD_G = 2;
 template <class TF, class TA, int NBW>
 __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const TA* P, int n, int k0, int kb, int n2,
                                                      int t) {
     typedef TA acc4 __attribute__((ext_vector_type(4)));
+    constexpr int NK = NBW / 4;
     const int lane = t & 63, wv = t >> 6, nwv = LU_THREADS / 64;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = (n2 + 15) / 16;
-    for (int tile = wv; tile < nt * nt; tile += nwv) {
-        const int r0 = (tile % nt) * 16, c0 = (tile / nt) * 16;
-        const bool rok = r0 + li < n2, cok = c0 + li < n2;
+    TF* a22 = a + (size_t)(k0 + kb) * n + k0 + kb;          // A22[r][c] = a22[c n + r]
+    const TA* l21 = P + kb;                                  // L21[r][k] = l21[k n + r]
+    for (int st = wv; st < nt; st += nwv) {
+        const int c0 = st * 16;
+        const bool cok = c0 + li < n2;
         const TF* ucol = a + (size_t)(k0 + kb + (cok ? c0 + li : 0)) * n + k0;
-        acc4 acc = {0, 0, 0, 0};
+        TA uv[NK];
 #pragma unroll
-        for (int kk = 0; kk < NBW; kk += 4) {
-            const int k = kk + lk;
-            const TA av = (rok && k < kb) ? -P[k * n + kb + r0 + li] : TA(0);
-            const TA bv = (cok && k < kb) ? (TA)ucol[k] : TA(0);
-            if constexpr (sizeof(TA) == 8)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            else
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        for (int q = 0; q < NK; ++q) {
+            const int k = 4 * q + lk;
+            uv[q] = (cok && k < kb) ? (TA)ucol[k] : TA(0);
         }
-        if (cok) {
-            TF* colp = a + (size_t)(k0 + kb + c0 + li) * n + k0 + kb;
+        int cc[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = (sizeof(TA) == 8) ? r0 + lk + 4 * i : r0 + 4 * lk + i;
-                if (r < n2) colp[r] = (TF)((TA)colp[r] + acc[i]);
+        for (int i = 0; i < 4; ++i) cc[i] = (sizeof(TA) == 8) ? c0 + lk + 4 * i : c0 + 4 * lk + i;
+        for (int r0 = 0; r0 < n2; r0 += 16 * UPD_G) {
+            acc4 acc[UPD_G];
+#pragma unroll
+            for (int g = 0; g < UPD_G; ++g) {
+                const int r = r0 + 16 * g + li;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[g][i] = (r < n2 && cc[i] < n2) ? (TA)a22[(size_t)cc[i] * n + r] : TA(0);
+            }
+#pragma unroll
+            for (int g = 0; g < UPD_G; ++g) {
+                const int r = r0 + 16 * g + li;
+#pragma unroll
+                for (int q = 0; q < NK; ++q) {
+                    const int k = 4 * q + lk;
+                    const TA lv = (r < n2 && k < kb) ? -l21[k * n + r] : TA(0);
+                    if constexpr (sizeof(TA) == 8)
+                        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(uv[q], lv, acc[g], 0, 0, 0);
+                    else
+                        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(uv[q], lv, acc[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < UPD_G; ++g) {
+                const int r = r0 + 16 * g + li;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (r < n2 && cc[i] < n2) a22[(size_t)cc[i] * n + r] = (TF)acc[g][i];
             }
         }
     }
@@ -235,11 +265,15 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
     __shared__ TA wv[LU_THREADS / 64];
     __shared__ int wr[LU_THREADS / 64];
     __shared__ int spiv[NBW];
+    // perm[r]: the row (relative to k0) whose content row r holds after the
+    // panel's exchanges so far
+    int* perm = reinterpret_cast<int*>(P + (size_t)NBW * n);
     TF* a = A + (size_t)blockIdx.x * n * n;
     int* pv = piv + (size_t)blockIdx.x * n;
     const int t = threadIdx.x;
     for (int k0 = 0; k0 < n; k0 += NBW) {
         const int kb = min(NBW, n - k0), m = n - k0;
+        for (int r = t; r < m; r += LU_THREADS) perm[r] = r;
         for (int idx = t; idx < m * kb; idx += LU_THREADS) {
             const int c = idx / m, r = idx % m;
             P[c * n + r] = (TA)a[(size_t)(k0 + c) * n + k0 + r];
@@ -257,6 +291,9 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
             if (t == 0) {
                 spiv[j] = p;
                 pv[k0 + j] = k0 + p;
+                const int x = perm[j];
+                perm[j] = perm[p];
+                perm[p] = x;
             }
             if (p != j && t < kb) {
                 const TA x = P[t * n + j];
@@ -277,25 +314,37 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
             const int c = idx / m, r = idx % m;
             a[(size_t)(k0 + c) * n + k0 + r] = (TF)P[c * n + r];
         }
-        // every other column, one thread each: the panel's row exchanges in
-        // order; a trailing column then gives its U12 = L11^-1 A12 entries
-        // (registers, written in place; the update reads them back through the cache)
+        // every other column, one thread each: the panel's row exchanges at
+        // once (the rows that change are 0..kb-1 and the pivot rows; all are
+        // read before any is written); a trailing column then gives its
+        // U12 = L11^-1 A12 entries (registers, written in place; the update
+        // reads them back through the cache)
         const int n2 = n - k0 - kb;
         for (int c = t; c < n; c += LU_THREADS) {
             if (c >= k0 && c < k0 + kb) continue;
-            TF* col = a + (size_t)c * n;
-            for (int j = 0; j < kb; ++j) {
-                const int p = spiv[j];
-                if (p != j) {
-                    const TF x = col[k0 + j];
-                    col[k0 + j] = col[k0 + p];
-                    col[k0 + p] = x;
-                }
+            TF* col = a + (size_t)c * n + k0;
+            TF y[NBW], z[NBW];
+#pragma unroll
+            for (int i = 0; i < NBW; ++i) y[i] = (i < kb) ? col[perm[i]] : TF(0);
+#pragma unroll
+            for (int j = 0; j < NBW; ++j) {
+                const int r = (j < kb) ? spiv[j] : 0;
+                z[j] = (r >= kb) ? col[perm[r]] : TF(0);
             }
-            if (c < k0 + kb) continue;
+#pragma unroll
+            for (int j = 0; j < NBW; ++j) {
+                const int r = (j < kb) ? spiv[j] : 0;
+                if (r >= kb) col[r] = z[j];
+            }
+            if (c < k0) {
+#pragma unroll
+                for (int i = 0; i < NBW; ++i)
+                    if (i < kb) col[i] = y[i];
+                continue;
+            }
             TA x[NBW];
 #pragma unroll
-            for (int i = 0; i < NBW; ++i) x[i] = (i < kb) ? (TA)col[k0 + i] : TA(0);
+            for (int i = 0; i < NBW; ++i) x[i] = (TA)y[i];
 #pragma unroll
             for (int i = 1; i < NBW; ++i)
 #pragma unroll
@@ -303,7 +352,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                     if (i < kb) x[i] -= P[q * n + i] * x[q];
 #pragma unroll
             for (int i = 0; i < NBW; ++i)
-                if (i < kb) col[k0 + i] = (TF)x[i];
+                if (i < kb) col[i] = (TF)x[i];
         }
         __syncthreads();
         if (n2 <= 0) break;
@@ -343,7 +392,7 @@ template <class TF>
 hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
     using C = LuCfg<TF>;
-    const size_t lds = (size_t)C::NBW * n * sizeof(typename C::TA);
+    const size_t lds = (size_t)C::NBW * n * sizeof(typename C::TA) + (size_t)n * sizeof(int);
     auto kern = lu_blocked_kernel<TF, typename C::TA, C::NBW>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
