@@ -19,6 +19,14 @@ namespace dg {
 constexpr int TS = 32;
 constexpr int SOLVE_THREADS = 64;
 
+// Factor and inverse entries are read once per apply, and the fine-level
+// factors (GBs) are far larger than the 256 MB last-level cache: nontemporal
+// loads stream them without evicting the vectors and operators that are
+// reused.  Blocks small enough to stay cached (FP32 coarse inverses) use
+// ordinary loads.
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+
 template <class TF>
 __global__ void __launch_bounds__(SOLVE_THREADS, 4)
     lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
@@ -39,7 +47,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             TF lrow[TS];
             const int li = (lane < kb) ? lane : 0;
 #pragma unroll
-            for (int j = 0; j < TS; ++j) lrow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li];
+            for (int j = 0; j < TS; ++j) lrow[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li]);
 #pragma unroll
             for (int j = 0; j < TS; ++j)
                 if (!(j < kb && lane < kb && lane > j)) lrow[j] = TF(0);
@@ -56,7 +64,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             // the panel's factor entries of this row, all loads in flight at once
             TF av[TS];
 #pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
+            for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
             double acc = x[row];
 #pragma unroll
             for (int j = 0; j < TS; ++j)
@@ -73,7 +81,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             TF urow[TS];
             const int ui = (lane < kb) ? lane : 0;
 #pragma unroll
-            for (int j = 0; j < TS; ++j) urow[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui];
+            for (int j = 0; j < TS; ++j) urow[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui]);
 #pragma unroll
             for (int j = 0; j < TS; ++j)
                 if (!(j < kb && lane < kb && lane <= j)) urow[j] = TF(0);
@@ -92,7 +100,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
         for (int row = t; row < k0; row += SOLVE_THREADS) {
             TF av[TS];
 #pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = a[(size_t)(k0 + (j < kb ? j : 0)) * n + row];
+            for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
             double acc = x[row];
 #pragma unroll
             for (int j = 0; j < TS; ++j)
@@ -146,7 +154,11 @@ __global__ void __launch_bounds__(GEMV_THREADS)
 #pragma unroll
         for (int k = 0; k < GEMV_ROWS; ++k) {
             const int i = lane + k * 64;
-            if (i < n) acc[k] = fma((double)c1[i], r1, fma((double)c0[i], r0, acc[k]));
+            if (i < n) {
+                const TF x0 = (sizeof(TF) == 8) ? ld_stream(&c0[i]) : c0[i];
+                const TF x1 = (sizeof(TF) == 8) ? ld_stream(&c1[i]) : c1[i];
+                acc[k] = fma((double)x1, r1, fma((double)x0, r0, acc[k]));
+            }
         }
     }
     for (; c < n; c += 4) {
@@ -155,7 +167,7 @@ __global__ void __launch_bounds__(GEMV_THREADS)
 #pragma unroll
         for (int k = 0; k < GEMV_ROWS; ++k) {
             const int i = lane + k * 64;
-            if (i < n) acc[k] = fma((double)c0[i], r0, acc[k]);
+            if (i < n) acc[k] = fma((double)((sizeof(TF) == 8) ? ld_stream(&c0[i]) : c0[i]), r0, acc[k]);
         }
     }
 #pragma unroll

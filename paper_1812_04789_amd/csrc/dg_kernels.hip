@@ -1516,7 +1516,10 @@ template <class SF, class AT>
 __device__ __forceinline__ void bsr_chunk(const SF* p, const AT* xv, AT& acc);
 template <>
 __device__ __forceinline__ void bsr_chunk<double, double>(const double* p, const double* xv, double& acc) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
+    // FP64 operators exceed the last-level cache: streamed with nontemporal
+    // loads so the gathered vectors and the Krylov basis stay cached
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
     acc = fma(a.x, xv[0], acc);
     acc = fma(a.y, xv[1], acc);
 }

@@ -295,15 +295,28 @@ static_assert(3 * GS_MAXK * RED_BLOCKS <= RED_BLOCKS * 256, "the partial buffer 
 // out[c] = sum_{b < nparts} part[c * nparts + b] for c < k <= 64, into LDS
 // (all threads see it after the call).  A group of g threads (a power of two,
 // g k <= blockDim.x, g <= 64) takes output c: thread i of the group sums
-// b = i, i + g, ..., then the group reduces by butterfly.  The order depends
-// only on (nparts, k, blockDim.x).
+// b = i, i + g, ... into eight accumulators (b = i + g (8 m + u) into u, the
+// eight loads of a round in flight together; the last partial round into
+// accumulator 0), adds them pairwise, then the group reduces by butterfly.  The order depends only on
+// (nparts, k, blockDim.x).
 __device__ __forceinline__ void sum_parts(const double* __restrict__ part, int nparts, int k, double* out) {
     int g = 64;
     while (g > 1 && g * k > (int)blockDim.x) g >>= 1;
     const int c = threadIdx.x / g, i = threadIdx.x % g;
-    double a = 0.0;
-    if (c < k)
-        for (int b = i; b < nparts; b += g) a += part[(size_t)c * nparts + b];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < k) {
+        const double* pc = part + (size_t)c * nparts;
+        int b = i;
+        for (; b + 7 * g < nparts; b += 8 * g) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = pc[b + u * g];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += x[u];
+        }
+        for (; b < nparts; b += g) acc[0] += pc[b];
+    }
+    double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     for (int o = g >> 1; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (c < k && i == 0) out[c] = a;
     __syncthreads();
