@@ -314,45 +314,57 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
             const int c = idx / m, r = idx % m;
             a[(size_t)(k0 + c) * n + k0 + r] = (TF)P[c * n + r];
         }
-        // every other column, one thread each: the panel's row exchanges at
-        // once (the rows that change are 0..kb-1 and the pivot rows; all are
-        // read before any is written); a trailing column then gives its
-        // U12 = L11^-1 A12 entries (registers, written in place; the update
-        // reads them back through the cache)
+        // every other column: the panel's row exchanges at once (rows 0..kb-1
+        // and the pivot rows change; each column's reads come before its
+        // writes) and, right of the panel, U12 = L11^-1 A12.  A group of NBW
+        // lanes takes a column, lane i its row i (coalesced column segments),
+        // CPI columns per group in flight; the unit-lower solve passes x_q
+        // down the group by shuffles, lane i holding row i of L11 in
+        // registers for the whole panel (the same operation order as a
+        // per-column forward substitution).
         const int n2 = n - k0 - kb;
-        for (int c = t; c < n; c += LU_THREADS) {
-            if (c >= k0 && c < k0 + kb) continue;
-            TF* col = a + (size_t)c * n + k0;
-            TF y[NBW], z[NBW];
+        {
+            constexpr int GW = NBW, NG = LU_THREADS / NBW, CPI = 4;
+            const int gi = t % GW, grp = t / GW;
+            const bool rowok = gi < kb;
+            TA lrow[GW];
 #pragma unroll
-            for (int i = 0; i < NBW; ++i) y[i] = (i < kb) ? col[perm[i]] : TF(0);
+            for (int q = 0; q < GW; ++q) lrow[q] = (rowok && q < gi) ? P[q * n + gi] : TA(0);
+            const int prow = rowok ? spiv[gi] : 0;
+            const bool zon = rowok && prow >= kb;
+            const int ysrc = rowok ? perm[gi] : 0;
+            const int zsrc = zon ? perm[prow] : 0;
+            const int ncol = n - kb;                    // columns outside the panel
+            for (int c0 = grp; c0 < ncol; c0 += NG * CPI) {
+                TF y[CPI], z[CPI];
+                TF* cols[CPI];
 #pragma unroll
-            for (int j = 0; j < NBW; ++j) {
-                const int r = (j < kb) ? spiv[j] : 0;
-                z[j] = (r >= kb) ? col[perm[r]] : TF(0);
+                for (int u = 0; u < CPI; ++u) {
+                    const int cr = c0 + u * NG;
+                    const int c = (cr < k0) ? cr : cr + kb;
+                    cols[u] = a + (size_t)(cr < ncol ? c : 0) * n + k0;
+                    y[u] = (cr < ncol && rowok) ? cols[u][ysrc] : TF(0);
+                    z[u] = (cr < ncol && zon) ? cols[u][zsrc] : TF(0);
+                }
+#pragma unroll
+                for (int u = 0; u < CPI; ++u)
+                    if (c0 + u * NG < ncol && zon) cols[u][prow] = z[u];
+                TA x[CPI];
+#pragma unroll
+                for (int u = 0; u < CPI; ++u) x[u] = (TA)y[u];
+#pragma unroll
+                for (int q = 0; q < GW - 1; ++q)
+#pragma unroll
+                    for (int u = 0; u < CPI; ++u) {
+                        const TA xq = __shfl(x[u], q, GW);
+                        x[u] -= lrow[q] * xq;
+                    }
+#pragma unroll
+                for (int u = 0; u < CPI; ++u) {
+                    const int cr = c0 + u * NG;
+                    if (cr < ncol && rowok) cols[u][gi] = (cr < k0) ? y[u] : (TF)x[u];
+                }
             }
-#pragma unroll
-            for (int j = 0; j < NBW; ++j) {
-                const int r = (j < kb) ? spiv[j] : 0;
-                if (r >= kb) col[r] = z[j];
-            }
-            if (c < k0) {
-#pragma unroll
-                for (int i = 0; i < NBW; ++i)
-                    if (i < kb) col[i] = y[i];
-                continue;
-            }
-            TA x[NBW];
-#pragma unroll
-            for (int i = 0; i < NBW; ++i) x[i] = (TA)y[i];
-#pragma unroll
-            for (int i = 1; i < NBW; ++i)
-#pragma unroll
-                for (int q = 0; q < i; ++q)
-                    if (i < kb) x[i] -= P[q * n + i] * x[q];
-#pragma unroll
-            for (int i = 0; i < NBW; ++i)
-                if (i < kb) col[i] = (TF)x[i];
         }
         __syncthreads();
         if (n2 <= 0) break;
