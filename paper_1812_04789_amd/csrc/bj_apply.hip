@@ -27,6 +27,47 @@ constexpr int SOLVE_THREADS = 64;
 template <class T>
 __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
 
+// x[row] -= sum_{j < kb} a[(k0 + j) n + row] x[k0 + j] for rows [r0, r1): the
+// panel's factor entries of a row, all loads of a lane in flight at once.
+// FP32 factors with an even leading dimension take two rows per lane
+// (8-byte loads, half the load instructions for the same bytes).
+template <class TF>
+__device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int n, int k0, int kb, int r0, int r1,
+                                           double* x, int t) {
+    if constexpr (sizeof(TF) == 4) {
+        if ((n & 1) == 0 && (r0 & 1) == 0) {
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            for (int row = r0 + 2 * t; row < r1; row += 2 * SOLVE_THREADS) {
+                f2v av[TS];
+#pragma unroll
+                for (int j = 0; j < TS; ++j)
+                    av[j] = ld_stream(reinterpret_cast<const f2v*>(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]));
+                double acc0 = x[row], acc1 = (row + 1 < r1) ? x[row + 1] : 0.0;
+#pragma unroll
+                for (int j = 0; j < TS; ++j)
+                    if (j < kb) {
+                        const double xj = x[k0 + j];
+                        acc0 -= (double)av[j].x * xj;
+                        acc1 -= (double)av[j].y * xj;
+                    }
+                x[row] = acc0;
+                if (row + 1 < r1) x[row + 1] = acc1;
+            }
+            return;
+        }
+    }
+    for (int row = r0 + t; row < r1; row += SOLVE_THREADS) {
+        TF av[TS];
+#pragma unroll
+        for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
+        double acc = x[row];
+#pragma unroll
+        for (int j = 0; j < TS; ++j)
+            if (j < kb) acc -= (double)av[j] * x[k0 + j];
+        x[row] = acc;
+    }
+}
+
 template <class TF>
 __global__ void __launch_bounds__(SOLVE_THREADS, 4)
     lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
@@ -60,17 +101,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
-        for (int row = k0 + kb + t; row < n; row += SOLVE_THREADS) {
-            // the panel's factor entries of this row, all loads in flight at once
-            TF av[TS];
-#pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
-            double acc = x[row];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (j < kb) acc -= (double)av[j] * x[k0 + j];
-            x[row] = acc;
-        }
+        panel_rows<TF>(a, n, k0, kb, k0 + kb, n, x, t);
         __syncthreads();
     }
     // backward, upper
@@ -97,16 +128,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
-        for (int row = t; row < k0; row += SOLVE_THREADS) {
-            TF av[TS];
-#pragma unroll
-            for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
-            double acc = x[row];
-#pragma unroll
-            for (int j = 0; j < TS; ++j)
-                if (j < kb) acc -= (double)av[j] * x[k0 + j];
-            x[row] = acc;
-        }
+        panel_rows<TF>(a, n, k0, kb, 0, k0, x, t);
         __syncthreads();
     }
     double* zb = z + (size_t)blockIdx.x * n;
