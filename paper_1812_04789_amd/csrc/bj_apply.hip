@@ -27,6 +27,20 @@ constexpr int SOLVE_THREADS = 64;
 template <class T>
 __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
 
+// Entry of a diagonal triangle, zero outside it.  FP64 factors read only the
+// triangle's own entries (lanes outside it issue no load: the lower and the
+// upper sweep each fetch their half of the tile); FP32 factors read the whole
+// tile row unconditionally and mask, which measures faster for 4-byte loads.
+template <class TF>
+__device__ __forceinline__ TF tri_load(const TF* __restrict__ a, size_t idx, bool in) {
+    if constexpr (sizeof(TF) == 8) {
+        return in ? ld_stream(&a[idx]) : TF(0);
+    } else {
+        const TF v = ld_stream(&a[idx]);
+        return in ? v : TF(0);
+    }
+}
+
 // x[row] -= sum_{j < kb} a[(k0 + j) n + row] x[k0 + j] for rows [r0, r1): the
 // panel's factor entries of a row, all loads of a lane in flight at once.
 // FP32 factors with an even leading dimension take two rows per lane
@@ -88,10 +102,8 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             TF lrow[TS];
             const int li = (lane < kb) ? lane : 0;
 #pragma unroll
-            for (int j = 0; j < TS; ++j) lrow[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li]);
-#pragma unroll
             for (int j = 0; j < TS; ++j)
-                if (!(j < kb && lane < kb && lane > j)) lrow[j] = TF(0);
+                lrow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li, j < kb && lane < kb && lane > j);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = 0; j < TS - 1; ++j) {
@@ -112,10 +124,8 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             TF urow[TS];
             const int ui = (lane < kb) ? lane : 0;
 #pragma unroll
-            for (int j = 0; j < TS; ++j) urow[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui]);
-#pragma unroll
             for (int j = 0; j < TS; ++j)
-                if (!(j < kb && lane < kb && lane <= j)) urow[j] = TF(0);
+                urow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui, j < kb && lane < kb && lane <= j);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = TS - 1; j >= 0; --j) {
