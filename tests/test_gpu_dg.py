@@ -111,10 +111,16 @@ def test_diag_blocks_parity(n, p, curved):
     assert np.linalg.norm(Bg - Bo) / np.linalg.norm(Bo) < 1e-12
 
 
-def test_batched_lu_parity():
-    rng = np.random.default_rng(7)
-    nblk, n = 6, 135
-    A = rng.standard_normal((nblk, n, n)) + 2.0 * np.eye(n)
+@pytest.mark.parametrize("n,shift", [(135, 2.0), (1, 0.0), (5, 0.0), (16, 0.0), (17, 0.0), (40, 0.0), (135, 0.0),
+                                     (320, 0.0), (320, 2.0)])
+def test_batched_lu_parity(n, shift):
+    """Blocked PLU against the oracle's partial pivoting: a single partial
+    panel (n < 16), an exact panel (16), a one-row remainder (17), the block
+    sizes of p = 1, 2, 3 (40, 135, 320) with ragged matrix-core tiles, and
+    unshifted random matrices whose pivots leave the panel."""
+    rng = np.random.default_rng(7 + n)
+    nblk = 6 if n <= 135 else 3
+    A = rng.standard_normal((nblk, n, n)) + shift * np.eye(n)
     LUo, pivo = olin.lu_factor(A)
     Ad = torch.tensor(np.ascontiguousarray(np.transpose(A, (0, 2, 1))), device="cuda")   # column-major
     piv = torch.zeros((nblk, n), dtype=torch.int32, device="cuda")
@@ -122,11 +128,14 @@ def test_batched_lu_parity():
     torch.cuda.synchronize()
     assert np.array_equal(piv.cpu().numpy(), pivo)
     LU = np.transpose(Ad.cpu().numpy(), (0, 2, 1))
-    assert np.abs(LU - LUo).max() < 1e-11
+    assert np.abs(LU - LUo).max() < 1e-11 * max(1.0, np.abs(LUo).max())
     b = rng.standard_normal((nblk, n))
     x = torch.empty(nblk * n, dtype=torch.float64, device="cuda")
     binding.batched_lu_solve(Ad, piv, _dev(b), x)
-    assert np.allclose(x.cpu().numpy().reshape(nblk, n), olin.lu_solve(LUo, pivo, b), rtol=1e-11, atol=1e-11)
+    xo = olin.lu_solve(LUo, pivo, b)
+    # two backward-stable solves differ by at most ~ n eps cond(A) relative
+    cond = max(np.linalg.cond(A[i]) for i in range(nblk))
+    assert _rel(x.cpu().numpy().reshape(nblk, n), xo) < 1e-15 * n * cond + 1e-14
 
 
 def test_free_stream_and_conservation_on_device():
