@@ -157,10 +157,10 @@ template hipError_t launch_extract_sub<float>(const double*, int, int, int, floa
 // Right-looking PLU with column panels.  The panel (rows k0..n-1) is factored
 // in LDS (pivot search, row exchange, scaling, rank-1 updates); every other
 // column then takes the panel's row exchanges and, right of the panel, its
-// U12 = L11^-1 A12 entries; the trailing matrix A22 -= L21 U12 is updated
-// with 4x4 register tiles.  Pivots are the partial-pivoting choices of the
-// unblocked kernel (max |a_ik|, lowest index on ties); only the summation
-// order of the trailing updates differs.
+// U12 = L11^-1 A12 entries; the trailing matrix A22 -= L21 U12 is updated on
+// the matrix cores.  Pivots are the partial-pivoting choices of the unblocked
+// kernel (max |a_ik|, lowest index on ties); only the summation order of the
+// trailing updates differs.
 
 // Largest |value| with the lowest row index on ties, over the block: a
 // butterfly inside each wavefront, then the wavefront winners in order.
