@@ -34,8 +34,12 @@ WORKLOADS = {
                            "FP64 pMG 3-2-1 (2+2 BJ sweeps, coarsest GMRES(BJ) 30), FGMRES(40) rtol 1e-8"),
     "tgv_p4_16_curved": dict(n=(16, 16, 16), lo=(0, 0, 0), hi=(2 * math.pi,) * 3, p=4, mach=0.01, mu=1.0 / 1600,
                              Pr=0.71, curved=0.05, ic="tgv", dt=0.05, levels=[4, 2, 1], restart=40, rtol=1e-8,
+                             # the FP64 unsteady residual bottoms out near 1e-7 of its initial value at
+                             # M = 0.01 (fluxes of size p0 |u| ~ 1e5 ||R|| are rounded): Newton stops at
+                             # 1e-6, the linear solves still go to 1e-8
+                             newton_rtol=1e-6,
                              desc="Taylor-Green NS/BR2 M=0.01 on a curved 16^3 hex mesh, p=4, one BDF2 step, "
-                                  "pMG 4-2-1, FGMRES(40) rtol 1e-8"),
+                                  "pMG 4-2-1, FGMRES(40) rtol 1e-8, Newton to 1e-6 of the initial residual"),
     "vortex_p2_4": dict(n=(4, 4, 4), lo=(0, 0, 0), hi=(10.0,) * 3, p=2, mach=0.5, mu=0.0, Pr=0.72, curved=0.0,
                         ic="vortex", dt=0.1, levels=[2], restart=30, rtol=1e-10,
                         desc="isentropic vortex Euler p=2 on a periodic 4^3 box, one BDF2 step dt=0.1, "
@@ -76,7 +80,7 @@ def run(args):
         Wn, Wnm1 = W.clone(), None
         stats = []
         for _ in range(K):
-            Wnp1, st = ctx.bdf2_step(Wn, Wnm1, wl["dt"], popts, fopts)
+            Wnp1, st = ctx.bdf2_step(Wn, Wnm1, wl["dt"], popts, fopts, newton_rtol=wl.get("newton_rtol", 1e-10))
             stats.append(st)
             Wnm1, Wn = Wn, Wnp1
         return Wn, stats
