@@ -6,7 +6,8 @@ configuration the benchmark times (single-case kernels, 16^3 meshes).
 * low-Mach Taylor-Green NS p = 4 on the curved 16^3 mesh (2,560,000 DOF):
   properties that hold at any size (the oracle needs minutes here):
   free-stream preservation, discrete conservation of the mean modes (to
-  rounding of the face fluxes), the
+  rounding of the face fluxes), and one BDF2 step of the workload (FP64 and
+  mixed precision) through the whole solver; the
   exact product linear in v, and the FD product of Eq. DG-mf within its
   truncation error of the exact product.
 """
@@ -98,4 +99,35 @@ def test_properties_full_size_tgv_p4_curved():
     err = _rel(yf, y1)
     print("16^3 p=4 curved: FD vs exact product %.3e" % err, flush=True)
     assert err < 1e-5
+    ctx.close()
+
+
+def test_bdf2_step_full_size_tgv_p4_curved():
+    """One BDF2 step of the curved 16^3 p = 4 M = 0.01 workload in the
+    benchmark's configuration (pMG 4-2-1, folded coarsest level, FGMRES(40) to
+    1e-8, Newton to 1e-6), FP64 and mixed (FP32 fine factors, BF16 coarse):
+    every linear solve reaches 1e-8 in the true residual, Newton converges,
+    and the mixed solution equals the FP64 one to 1e-10 relative."""
+    vtx = inputs.box_vertices(N16, (0, 0, 0), (L, L, L), amp=0.05)
+    ctx = binding.Context(N16, (0, 0, 0), (L, L, L), 4, vertices=vtx, **GAS)
+    W0 = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.01)))
+    fo = binding.fgmres_opts(restart=40, rtol=1e-8)
+    out = {}
+    for name, fine, coarse in (("fp64", binding.DG_FP64, binding.DG_FP64), ("mixed", binding.DG_FP32, binding.DG_BF16)):
+        po = binding.pmg_opts([4, 2, 1], prec_fine=fine, prec_coarse=coarse, coarse_matrix_free=2)
+        W1, st = ctx.bdf2_step(W0, None, 0.05, po, fo, newton_rtol=1e-6)
+        print("%s: newton %d, FGMRES %d, true rel res %.2e, Newton %.2e of the initial residual" %
+              (name, st.newton, st.linear_iters, st.max_rel_res_true, st.res_final / st.res0), flush=True)
+        assert st.max_rel_res_true <= 1e-8
+        assert st.res_final <= 1e-6 * st.res0
+        out[name] = W1.cpu().numpy()
+    w0 = W0.cpu().numpy()
+    assert _rel(out["fp64"], w0) > 1e-8                       # the step moved the state
+    err = _rel(out["mixed"], out["fp64"])
+    # the state is dominated by the total energy (p0 ~ 7e3): compare the
+    # increments as well, which carry the flow's change over the step
+    derr = _rel(out["mixed"] - w0, out["fp64"] - w0)
+    print("mixed vs FP64 solution %.2e, increment %.2e" % (err, derr), flush=True)
+    assert err < 1e-10
+    assert derr < 1e-7          # two solves to 1e-8 in the residual (measured 4e-10)
     ctx.close()
