@@ -6,10 +6,10 @@ configuration the benchmark times (single-case kernels, 16^3 meshes).
 * low-Mach Taylor-Green NS p = 4 on the curved 16^3 mesh (2,560,000 DOF):
   properties that hold at any size (the oracle needs minutes here):
   free-stream preservation, discrete conservation of the mean modes (to
-  rounding of the face fluxes), and one BDF2 step of the workload (FP64 and
-  mixed precision) through the whole solver; the
-  exact product linear in v, and the FD product of Eq. DG-mf within its
-  truncation error of the exact product.
+  rounding of the face fluxes), the exact product linear in v, the FD
+  product of Eq. DG-mf within its truncation error of the exact product, and
+  one BDF2 step of the workload (FP64 and mixed precision) through the whole
+  solver.
 """
 import math
 
