@@ -229,7 +229,12 @@ __device__ __forceinline__ void face_penalty_symmetry(const T up[5], const T um[
     }
 }
 
-template <class T, bool NS>
+// FIX (dual-number block columns only): FIX_NBR, the neighbour's state does
+// not move; FIX_OWN, this element's state does not move.  The fixed side's
+// half of the averaged viscous flux then has no tangent and is skipped, so
+// only the tangent parts of fo are valid.
+constexpr int FIX_NONE = 0, FIX_NBR = 1, FIX_OWN = 2;
+template <class T, bool NS, int FIX = FIX_NONE>
 __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3], const T um[5], const T gxm[5][3],
                                                const double nrm[3], const double Jip[3][3], const double Jim[3][3],
                                                double lam_p, double lam_m, double sc, const Gas& gas, T* fo) {
@@ -237,7 +242,7 @@ __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3],
     roe_flux(up, um, nrm, gas.gamma, Fn);
     if constexpr (NS) {
         // averaged viscous flux, normal component only: 1/2 (F_v(u+, g+) + F_v(u-, g-)).n
-        {
+        if constexpr (FIX != FIX_OWN) {
             T g[5][3];
 #pragma unroll
             for (int a = 0; a < 5; ++a)
@@ -246,7 +251,7 @@ __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3],
                     g[a][j] = Jip[0][j] * gxp[a][0] + Jip[1][j] * gxp[a][1] + Jip[2][j] * gxp[a][2];
             flux_v_n_acc(up, g, gas, 0.5, nrm, Fn);
         }
-        {
+        if constexpr (FIX != FIX_NBR) {
             T g[5][3];
 #pragma unroll
             for (int a = 0; a < 5; ++a)
@@ -1408,8 +1413,8 @@ __global__ void __launch_bounds__(256) offdiag_kernel(MeshDev m, Gas gas, const 
                     Jim[k / 3][k % 3] = sGe[fq][13 + k];
                 }
                 Dual fo[20];
-                face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, sGe[fq][22], sGe[fq][23], sGe[fq][24], gas,
-                                         fo);
+                face_integrand<Dual, NS, FIX_OWN>(up, gxp, um, gxm, nrm, Jip, Jim, sGe[fq][22], sGe[fq][23],
+                                                  sGe[fq][24], gas, fo);
                 for (int k = 0; k < 20; ++k) sOut[t][k] = fo[k].d;
             }
         }
@@ -1744,7 +1749,10 @@ struct SzD {
 };
 template <int P> struct LaunchD { static constexpr int EPB = (P == 1) ? 8 : ((P == 2) ? 2 : 1); };
 
-template <int P, bool NS, bool CURVED>
+// SELF: some axis has a single element, so a face's neighbour can be the
+// element itself and its trace moves with the column; otherwise the
+// neighbour traces are fixed and their half of the viscous average is skipped.
+template <int P, bool NS, bool CURVED, bool SELF>
 __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
     diag_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ nbrtr, double shift,
                 double* __restrict__ out) {
@@ -1879,7 +1887,8 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
                 gxp[a][1] = Dual(g1, on ? bgp[1] : 0.0);
                 gxp[a][2] = Dual(g2, on ? bgp[2] : 0.0);
             }
-            if (nb == e) {
+            const bool self_nb = SELF && nb == e;
+            if (self_nb) {
                 // one-element periodic axis: the neighbour trace is this element's
                 // trace on the opposite face, and it moves with W_e
                 double bvm, bgm[3];
@@ -1919,8 +1928,17 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
             }
             (void)t1;
             Dual fo[20];
-            face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
-                                     fo);
+            if constexpr (SELF) {
+                if (self_nb)
+                    face_integrand<Dual, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m,
+                                             tb.w[qt1] * tb.w[qt2] * JF, gas, fo);
+                else
+                    face_integrand<Dual, NS, FIX_NBR>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m,
+                                                      tb.w[qt1] * tb.w[qt2] * JF, gas, fo);
+            } else {
+                face_integrand<Dual, NS, FIX_NBR>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m,
+                                                  tb.w[qt1] * tb.w[qt2] * JF, gas, fo);
+            }
             double* so = sF + q * 20;
 #pragma unroll
             for (int k = 0; k < 20; ++k) so[k] = fo[k].d;
@@ -1991,6 +2009,19 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
 }
 
 namespace {
+template <int P, bool SELF>
+hipError_t launch_diag_k(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr, dim3 grid,
+                         dim3 block, bool curved, hipStream_t s) {
+    if (a.ns) {
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, true, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        else hipLaunchKernelGGL((diag_kernel<P, true, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+    } else {
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, false, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        else hipLaunchKernelGGL((diag_kernel<P, false, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+    }
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
                          hipStream_t s) {
@@ -2001,14 +2032,9 @@ hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double*
     constexpr int EPB = LaunchD<P>::EPB;
     dim3 grid((a.m.ne + EPB - 1) / EPB, 5 * NQ), block(EPB * NQ);
     const bool curved = a.m.vtx != nullptr;
-    if (a.ns) {
-        if (curved) hipLaunchKernelGGL((diag_kernel<P, true, true>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-        else hipLaunchKernelGGL((diag_kernel<P, true, false>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-    } else {
-        if (curved) hipLaunchKernelGGL((diag_kernel<P, false, true>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-        else hipLaunchKernelGGL((diag_kernel<P, false, false>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-    }
-    return hipGetLastError();
+    const bool self = a.m.nx == 1 || a.m.ny == 1 || a.m.nz == 1;
+    if (self) return launch_diag_k<P, true>(a, W, shift, blocks, nbrtr, grid, block, curved, s);
+    return launch_diag_k<P, false>(a, W, shift, blocks, nbrtr, grid, block, curved, s);
 }
 }  // namespace
 
