@@ -1566,6 +1566,16 @@ __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const
     const size_t glast = min(g0 + blockDim.x, nrows) - 1;
     const int e_first = (int)(g0 / nbc);
     const int nel = (int)(glast / nbc) - e_first + 1;
+    const size_t g = g0 + threadIdx.x;
+    // the row's entries of the first DOTS_PRE basis vectors, requested before
+    // the gather so that their latency overlaps the product (the Arnoldi
+    // dots at the end otherwise start with a cold round trip)
+    constexpr int DOTS_PRE = 16;
+    double vpre[DOTS_PRE];
+    if constexpr (DOTS) {
+#pragma unroll
+        for (int c = 0; c < DOTS_PRE; ++c) vpre[c] = (g < nrows && c < k) ? Vb[(size_t)c * nrows + g] : 0.0;
+    }
     for (int i = threadIdx.x; i < nel * NBLK * ldr; i += blockDim.x) {
         const int c = i % ldr, t = i / ldr, f = t % NBLK, le = t / NBLK;
         const int e = e_first + le;
@@ -1573,7 +1583,6 @@ __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const
         xs[i] = (c < nbc) ? (AT)x[(size_t)src * nbc + c] : (AT)0;
     }
     __syncthreads();
-    const size_t g = g0 + threadIdx.x;
     double yg = 0.0;
     if (g < nrows) {
         const int e = (int)(g / nbc);
@@ -1597,12 +1606,14 @@ __global__ void __launch_bounds__(256) bsr_rows_kernel(MeshDev m, int nbc, const
     if constexpr (DOTS) {
         // first Gram-Schmidt pass of the Arnoldi step on this block's rows
         constexpr int CH = 16;
+        static_assert(CH == DOTS_PRE, "the first chunk is the prefetched one");
         __shared__ double sh[4 * CH];
         for (int c0 = 0; c0 < k; c0 += CH) {
             double dv[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                dv[c] = (g < nrows && c0 + c < k) ? Vb[(size_t)(c0 + c) * nrows + g] * yg : 0.0;
+                dv[c] = (c0 == 0) ? vpre[c] * yg
+                                  : ((g < nrows && c0 + c < k) ? Vb[(size_t)(c0 + c) * nrows + g] * yg : 0.0);
             block_sum_cols<CH>(dv, min(CH, k - c0), sh, part + (size_t)c0 * gridDim.x + blockIdx.x, gridDim.x);
         }
     }
