@@ -202,6 +202,8 @@ template <class TF, class TA, int NBW>
 __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const TA* P, int n, int k0, int kb, int n2,
                                                      int t) {
     typedef TA acc4 __attribute__((ext_vector_type(4)));
+    static_assert(NBW % 4 == 0, "the panel width is a multiple of the instruction's K = 4");
+    static_assert(LU_THREADS % 64 == 0, "whole wavefronts");
     constexpr int NK = NBW / 4;
     const int lane = t & 63, wv = t >> 6, nwv = LU_THREADS / 64;
     const int li = lane & 15, lk = lane >> 4;
@@ -325,6 +327,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         const int n2 = n - k0 - kb;
         {
             constexpr int GW = NBW, NG = LU_THREADS / NBW, CPI = 4;
+            static_assert(64 % GW == 0, "a lane group lies inside one wavefront (shuffle width)");
             const int gi = t % GW, grp = t / GW;
             const bool rowok = gi < kb;
             TA lrow[GW];
