@@ -1,7 +1,8 @@
 // Block-Jacobi apply of the smoother (Sec. 6.3; Alg. 2 SMOOTH): z = D^-1 r
 // for every element block, either by the two triangular solves with the PLU
 // factors or by a product with the explicit block inverse.  Factor storage is
-// double or float (column-major a[col*n + row]); vectors and the arithmetic
+// double or float, column-major: a[col*ld + row] with ld >= n for the
+// triangular solves, ld = n for the inverses; vectors and the arithmetic
 // of the apply are FP64.  These kernels stream the factors once per apply and
 // are bound by HBM bandwidth.
 #include "internal.h"
@@ -41,21 +42,23 @@ __device__ __forceinline__ TF tri_load(const TF* __restrict__ a, size_t idx, boo
     }
 }
 
-// x[row] -= sum_{j < kb} a[(k0 + j) n + row] x[k0 + j] for rows [r0, r1): the
+// x[row] -= sum_{j < kb} a[(k0 + j) ld + row] x[k0 + j] for rows [r0, r1): the
 // panel's factor entries of a row, all loads of a lane in flight at once.
 // FP32 factors with an even leading dimension take two rows per lane
 // (8-byte loads, half the load instructions for the same bytes).
 template <class TF>
-__device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int n, int k0, int kb, int r0, int r1,
+__device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int ld, int k0, int kb, int r0, int r1,
                                            double* x, int t) {
     if constexpr (sizeof(TF) == 4) {
-        if ((n & 1) == 0 && (r0 & 1) == 0) {
+        // (with r1 odd the last pair's second row lies in the column's
+        // padding, ld > n: loaded, never used)
+        if ((ld & 1) == 0 && (r0 & 1) == 0) {
             typedef float f2v __attribute__((ext_vector_type(2)));
             for (int row = r0 + 2 * t; row < r1; row += 2 * SOLVE_THREADS) {
                 f2v av[TS];
 #pragma unroll
                 for (int j = 0; j < TS; ++j)
-                    av[j] = ld_stream(reinterpret_cast<const f2v*>(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]));
+                    av[j] = ld_stream(reinterpret_cast<const f2v*>(&a[(size_t)(k0 + (j < kb ? j : 0)) * ld + row]));
                 double acc0 = x[row], acc1 = (row + 1 < r1) ? x[row + 1] : 0.0;
 #pragma unroll
                 for (int j = 0; j < TS; ++j)
@@ -73,7 +76,7 @@ __device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int n, int 
     for (int row = r0 + t; row < r1; row += SOLVE_THREADS) {
         TF av[TS];
 #pragma unroll
-        for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * n + row]);
+        for (int j = 0; j < TS; ++j) av[j] = ld_stream(&a[(size_t)(k0 + (j < kb ? j : 0)) * ld + row]);
         double acc = x[row];
 #pragma unroll
         for (int j = 0; j < TS; ++j)
@@ -85,9 +88,9 @@ __device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int n, int 
 template <class TF>
 __global__ void __launch_bounds__(SOLVE_THREADS, 4)
     lu_solve_blocked_kernel(const TF* __restrict__ LU, const int* __restrict__ pos, const double* __restrict__ r,
-                            double* __restrict__ z, int n) {
+                            double* __restrict__ z, int n, int ld) {
     extern __shared__ double x[];
-    const TF* a = LU + (size_t)blockIdx.x * n * n;
+    const TF* a = LU + (size_t)blockIdx.x * n * ld;        // column c at a + c ld
     const int* po = pos + (size_t)blockIdx.x * n;
     const double* rb = r + (size_t)blockIdx.x * n;
     const int t = threadIdx.x;
@@ -103,7 +106,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             const int li = (lane < kb) ? lane : 0;
 #pragma unroll
             for (int j = 0; j < TS; ++j)
-                lrow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * n + k0 + li, j < kb && lane < kb && lane > j);
+                lrow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * ld + k0 + li, j < kb && lane < kb && lane > j);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = 0; j < TS - 1; ++j) {
@@ -113,7 +116,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
-        panel_rows<TF>(a, n, k0, kb, k0 + kb, n, x, t);
+        panel_rows<TF>(a, ld, k0, kb, k0 + kb, n, x, t);
         __syncthreads();
     }
     // backward, upper
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             const int ui = (lane < kb) ? lane : 0;
 #pragma unroll
             for (int j = 0; j < TS; ++j)
-                urow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * n + k0 + ui, j < kb && lane < kb && lane <= j);
+                urow[j] = tri_load(a, (size_t)(k0 + (j < kb ? j : 0)) * ld + k0 + ui, j < kb && lane < kb && lane <= j);
             double xi = (lane < kb) ? x[k0 + lane] : 0.0;
 #pragma unroll
             for (int j = TS - 1; j >= 0; --j) {
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
             if (lane < kb) x[k0 + lane] = xi;
         }
         __syncthreads();
-        panel_rows<TF>(a, n, k0, kb, 0, k0, x, t);
+        panel_rows<TF>(a, ld, k0, kb, 0, k0, x, t);
         __syncthreads();
     }
     double* zb = z + (size_t)blockIdx.x * n;
@@ -146,16 +149,17 @@ __global__ void __launch_bounds__(SOLVE_THREADS, 4)
 }
 
 template <class TF>
-hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
+hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n, int ld,
                                    hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
+    if (ld < n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(lu_solve_blocked_kernel<TF>, dim3(nblk), dim3(SOLVE_THREADS), n * sizeof(double), s, LU, pos,
-                       r, z, n);
+                       r, z, n, ld);
     return hipGetLastError();
 }
-template hipError_t launch_lu_solve_blocked<double>(const double*, const int*, const double*, double*, int, int,
+template hipError_t launch_lu_solve_blocked<double>(const double*, const int*, const double*, double*, int, int, int,
                                                     hipStream_t);
-template hipError_t launch_lu_solve_blocked<float>(const float*, const int*, const double*, double*, int, int,
+template hipError_t launch_lu_solve_blocked<float>(const float*, const int*, const double*, double*, int, int, int,
                                                    hipStream_t);
 
 // z = X r per block with the explicit inverse (column-major, storage TF).

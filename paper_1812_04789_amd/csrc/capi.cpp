@@ -80,6 +80,7 @@ struct Krylov {
 
 struct Level {
     int p = 0, nv = 0, nb = 0;
+    int ld = 0;           // leading dimension of the factors (fine_block_ld(nb) on level 0, else nb)
     size_t ndof = 0;
     DBuf<double> f64;     // factors (FP64)
     DBuf<float> f32;      // factors (FP32)
@@ -226,8 +227,8 @@ void bj_apply(dg_ctx* ctx, int l, const double* r, double* z) {
         if (L.inv)
             return L.use32 ? launch_inv_gemv<float>(L.inv32.p, r, z, ctx->ne, L.nb, ctx->s)
                            : launch_inv_gemv<double>(L.inv64.p, r, z, ctx->ne, L.nb, ctx->s);
-        return L.use32 ? launch_lu_solve_blocked<float>(L.f32.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s)
-                       : launch_lu_solve_blocked<double>(L.f64.p, L.pos.p, r, z, ctx->ne, L.nb, ctx->s);
+        return L.use32 ? launch_lu_solve_blocked<float>(L.f32.p, L.pos.p, r, z, ctx->ne, L.nb, L.ld, ctx->s)
+                       : launch_lu_solve_blocked<double>(L.f64.p, L.pos.p, r, z, ctx->ne, L.nb, L.ld, ctx->s);
     });
 }
 
@@ -484,10 +485,10 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     CK(launch_copy(N, W, ctx->W0.p, ctx->s));
     CK(launch_residual(ctx->a, ctx->W0.p, ctx->RW0.p, ctx->s));
     dot(ctx, ctx->W0.p, ctx->W0.p, N, sc(ctx, S_PMG_NW2));
-    const int nb = ctx->nb;
-    ctx->blk.ensure((size_t)ctx->ne * nb * nb);
+    const int nb = ctx->nb, ld0 = fine_block_ld(nb);
+    ctx->blk.ensure((size_t)ctx->ne * nb * ld0);
     ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
-    timed(ctx, DG_K_DIAG_BLOCKS, 8.0 * ctx->ne * (double)nb * nb + 8.0 * (double)ctx->N, 0.0, [&] { return launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ctx->nbrtr.p, ctx->s); });
+    timed(ctx, DG_K_DIAG_BLOCKS, 8.0 * ctx->ne * (double)nb * nb + 8.0 * (double)ctx->N, 0.0, [&] { return launch_diag_blocks(ctx->a, ctx->W0.p, shift, ctx->blk.p, ld0, ctx->nbrtr.p, ctx->s); });
     for (size_t l = o->n_levels; l < ctx->lv.size(); ++l) ctx->lv[l].release();
     ctx->lv.resize(o->n_levels);
     for (int l = 0; l < o->n_levels; ++l) {
@@ -495,6 +496,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         L.p = o->p_level[l];
         L.nv = (L.p + 1) * (L.p + 1) * (L.p + 1);
         L.nb = 5 * L.nv;
+        L.ld = (l == 0) ? ld0 : L.nb;
         L.ndof = (size_t)ctx->ne * L.nb;
         L.use32 = (l == 0) ? (o->prec_fine == DG_FP32) : (o->prec_coarse != DG_FP64);
         L.assembled = l > 0 && (o->coarse_matrix_free == 0 ||
@@ -519,22 +521,23 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
             // inherited operator K_l = P^T K_0 P: diagonal sub-blocks + face-coupling blocks
             ctx->dtmp.ensure(sz);
             ctx->otmp.ensure(6 * sz);
-            CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
+            CK(launch_extract_sub<double>(ctx->blk.p, nb, ld0, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
             CK(launch_offdiag_blocks(ctx->a, ctx->W0.p, L.p, ctx->otmp.p, ctx->s));
             if (!L.fold) pack_operator(ctx, L, 7);
         }
         if (L.use32) {
-            L.f32.ensure(sz);
-            if (l == 0) CK(launch_convert_fp64_to_fp32(ctx->blk.p, L.f32.p, sz, ctx->s));
-            else CK(launch_extract_sub<float>(ctx->blk.p, nb, ctx->nv, L.nv, L.f32.p, ctx->ne, ctx->s));
-            timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 4.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<float>(L.f32.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
+            const size_t szl = (size_t)ctx->ne * L.nb * L.ld;
+            L.f32.ensure(szl);
+            if (l == 0) CK(launch_convert_fp64_to_fp32(ctx->blk.p, L.f32.p, szl, ctx->s));
+            else CK(launch_extract_sub<float>(ctx->blk.p, nb, ld0, ctx->nv, L.nv, L.f32.p, ctx->ne, ctx->s));
+            timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 4.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<float>(L.f32.p, L.piv.p, L.pos.p, ctx->ne, L.nb, L.ld, ctx->s); });
         } else {
             if (l == 0) {
-                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(ctx->blk.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
+                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(ctx->blk.p, L.piv.p, L.pos.p, ctx->ne, L.nb, L.ld, ctx->s); });
             } else {
                 L.f64.ensure(sz);
-                CK(launch_extract_sub<double>(ctx->blk.p, nb, ctx->nv, L.nv, L.f64.p, ctx->ne, ctx->s));
-                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(L.f64.p, L.piv.p, L.pos.p, ctx->ne, L.nb, ctx->s); });
+                CK(launch_extract_sub<double>(ctx->blk.p, nb, ld0, ctx->nv, L.nv, L.f64.p, ctx->ne, ctx->s));
+                timed(ctx, DG_K_LU, lu_bytes(ctx, L.nb, 8.0), lu_flops(ctx, L.nb), [&] { return launch_lu_blocked<double>(L.f64.p, L.piv.p, L.pos.p, ctx->ne, L.nb, L.ld, ctx->s); });
             }
         }
         if (L.fold) {
@@ -773,7 +776,7 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
     // Krylov workspace of restart m on n entries (basis V, directions Z, Hessenberg and rotations)
     auto krylov = [](double m, double n) { return (2 * m + 1) * n * 8 + ((m + 1) * m + 5 * m + 2 + 8) * 8; };
     double b = 24 * ne * 8 + (double)RED_BLOCKS * 256 * 8 + S_COUNT * 8 + 4 * 4 + 3 * N * 8;   // create
-    b += 2 * N * 8 + ne * nb * nb * 8 + (double)nbr_trace_size(p, (int)ne) * 8;  // W0, RW0, blocks, traces
+    b += 2 * N * 8 + ne * nb * fine_block_ld((int)nb) * 8 + (double)nbr_trace_size(p, (int)ne) * 8;  // W0, RW0, blocks, traces
     double tmp = 0.0;
     for (int l = 0; l < po->n_levels; ++l) {
         const int pl = po->p_level[l];
@@ -789,7 +792,7 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
             b += (double)bsr_entries((int)ne, (int)nbl, fold ? 6 : 7) *
                  (po->prec_coarse == DG_FP64 ? 8 : (po->prec_coarse == DG_FP32 ? 4 : 2));
         }
-        if (use32) b += sz * 4;
+        if (use32) b += (l == 0 ? ne * nbl * fine_block_ld((int)nbl) : sz) * 4;
         else if (l > 0) b += sz * 8;
         if (nbl <= INV_POLICY_N) b += sz * (use32 ? 4 : 8);
         if (l == po->n_levels - 1 && po->n_levels > 1)
@@ -991,7 +994,7 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
         need(ctx, W, "W");
         need(ctx, blocks, "blocks");
         ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
-        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->nbrtr.p, ctx->s));
+        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->nb, ctx->nbrtr.p, ctx->s));
     });
 }
 
@@ -1006,7 +1009,7 @@ dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off) 
 
 dg_status dg_batched_lu(void* hip_stream, double* A, int* piv, int nblk, int n) {
     if (!A || !piv || nblk < 0 || n < 1 || n > 625) return DG_EINVAL;
-    if (launch_lu_blocked<double>(A, piv, nullptr, nblk, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
+    if (launch_lu_blocked<double>(A, piv, nullptr, nblk, n, n, (hipStream_t)hip_stream) != hipSuccess) return DG_EHIP;
     return DG_OK;
 }
 

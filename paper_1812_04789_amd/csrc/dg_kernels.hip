@@ -1766,7 +1766,7 @@ template <int P> struct LaunchD { static constexpr int EPB = (P == 1) ? 8 : ((P 
 template <int P, bool NS, bool CURVED, bool SELF>
 __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
     diag_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ nbrtr, double shift,
-                double* __restrict__ out) {
+                double* __restrict__ out, int ld) {
     using S_ = SzD<P>;
     constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NB = 5 * NQ;
     constexpr int EPB = LaunchD<P>::EPB;
@@ -2014,28 +2014,29 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], Y2[a * NQ + tix_dir<N>(2, j, ii)], acc);
-            out[((size_t)e * NB + col) * NB + a * NQ + pm] = acc;
+            out[((size_t)e * NB + col) * ld + a * NQ + pm] = acc;
         }
     }
 }
 
 namespace {
 template <int P, bool SELF>
-hipError_t launch_diag_k(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr, dim3 grid,
-                         dim3 block, bool curved, hipStream_t s) {
+hipError_t launch_diag_k(const DGArgs& a, const double* W, double shift, double* blocks, int ld, double* nbrtr,
+                         dim3 grid, dim3 block, bool curved, hipStream_t s) {
     if (a.ns) {
-        if (curved) hipLaunchKernelGGL((diag_kernel<P, true, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-        else hipLaunchKernelGGL((diag_kernel<P, true, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, true, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks, ld);
+        else hipLaunchKernelGGL((diag_kernel<P, true, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks, ld);
     } else {
-        if (curved) hipLaunchKernelGGL((diag_kernel<P, false, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
-        else hipLaunchKernelGGL((diag_kernel<P, false, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks);
+        if (curved) hipLaunchKernelGGL((diag_kernel<P, false, true, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks, ld);
+        else hipLaunchKernelGGL((diag_kernel<P, false, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks, ld);
     }
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double* blocks, int ld, double* nbrtr,
                          hipStream_t s) {
+    if (ld < 5 * (P + 1) * (P + 1) * (P + 1)) return hipErrorInvalidValue;
     constexpr int NQ = (P + 1) * (P + 1) * (P + 1);
     hipLaunchKernelGGL(nbr_trace_kernel<P>, dim3(a.m.ne), dim3(256), 0, s, a.m, W, nbrtr);
     hipError_t e = hipGetLastError();
@@ -2044,20 +2045,20 @@ hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double*
     dim3 grid((a.m.ne + EPB - 1) / EPB, 5 * NQ), block(EPB * NQ);
     const bool curved = a.m.vtx != nullptr;
     const bool self = a.m.nx == 1 || a.m.ny == 1 || a.m.nz == 1;
-    if (self) return launch_diag_k<P, true>(a, W, shift, blocks, nbrtr, grid, block, curved, s);
-    return launch_diag_k<P, false>(a, W, shift, blocks, nbrtr, grid, block, curved, s);
+    if (self) return launch_diag_k<P, true>(a, W, shift, blocks, ld, nbrtr, grid, block, curved, s);
+    return launch_diag_k<P, false>(a, W, shift, blocks, ld, nbrtr, grid, block, curved, s);
 }
 }  // namespace
 
 size_t nbr_trace_size(int p, int ne) { return (size_t)ne * 6 * (p + 1) * (p + 1) * 20; }
 
-hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, int ld, double* nbrtr,
                               hipStream_t s) {
     switch (a.p) {
-        case 1: return launch_diag_p<1>(a, W, shift, blocks, nbrtr, s);
-        case 2: return launch_diag_p<2>(a, W, shift, blocks, nbrtr, s);
-        case 3: return launch_diag_p<3>(a, W, shift, blocks, nbrtr, s);
-        case 4: return launch_diag_p<4>(a, W, shift, blocks, nbrtr, s);
+        case 1: return launch_diag_p<1>(a, W, shift, blocks, ld, nbrtr, s);
+        case 2: return launch_diag_p<2>(a, W, shift, blocks, ld, nbrtr, s);
+        case 3: return launch_diag_p<3>(a, W, shift, blocks, ld, nbrtr, s);
+        case 4: return launch_diag_p<4>(a, W, shift, blocks, ld, nbrtr, s);
         default: return hipErrorInvalidValue;
     }
 }

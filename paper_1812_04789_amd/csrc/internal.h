@@ -60,8 +60,10 @@ hipError_t launch_jvp_fd(const DGArgs& a, const double* W, const double* RW, con
                          double shift, double* y, hipStream_t s);
 hipError_t launch_jvp_exact(const DGArgs& a, const double* W, const double* v, double shift, double* y,
                             hipStream_t s);
-// nbrtr: scratch of nbr_trace_size(p, ne) doubles (neighbour traces at the face points)
-hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, double* nbrtr,
+// nbrtr: scratch of nbr_trace_size(p, ne) doubles (neighbour traces at the face points);
+// blocks: ne column-major blocks of nb columns with leading dimension ld >= nb
+// (block e at blocks + e nb ld)
+hipError_t launch_diag_blocks(const DGArgs& a, const double* W, double shift, double* blocks, int ld, double* nbrtr,
                               hipStream_t s);
 size_t nbr_trace_size(int p, int ne);
 // Coarse face-coupling blocks: for every element e, face f, the (nbc x nbc)
@@ -155,11 +157,12 @@ template <class TF>
 hipError_t launch_lu_solve(const TF* LU, const int* piv, const double* r, double* z, int nblk, int n,
                            hipStream_t s);
 // Blocked PLU (same pivots) plus the gather index pos of the row permutation;
-// the blocked solve takes pos.  Dynamic LDS 2*16*n doubles (n <= 625).
+// the blocked solve takes pos.  Blocks are column-major with leading
+// dimension ld >= n (block b at A + b n ld; rows n..ld-1 are never touched).
 template <class TF>
-hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s);
+hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, int ld, hipStream_t s);
 template <class TF>
-hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n,
+hipError_t launch_lu_solve_blocked(const TF* LU, const int* pos, const double* r, double* z, int nblk, int n, int ld,
                                    hipStream_t s);
 // Explicit inverse of PLU-factored blocks (n <= 320): FP64 workspace Xw
 // [nblk][n][n]; Xout (TF, may be null when TF is double and Xw is used directly).
@@ -169,9 +172,15 @@ template <class TF>
 hipError_t launch_inv_gemv(const TF* X, const double* r, double* z, int nblk, int n, hipStream_t s);
 constexpr int INV_MAX_N = 320;
 constexpr int INV_POLICY_N = 135;     // the smoother applies an explicit inverse up to this block size
-// Extract coarse principal sub-blocks (FP64 column-major fine blocks) and round to TF.
+// Leading dimension of the fine-level blocks: blocks applied by the triangular
+// solves (nb > INV_POLICY_N) start every column on a 128-byte line (nb = 625 at
+// p = 4 becomes 640; nb = 320 is unchanged); inverse-path blocks stay packed.
+inline int fine_block_ld(int nb) { return (nb > INV_POLICY_N) ? (nb + 15) / 16 * 16 : nb; }
+// Extract coarse principal sub-blocks (FP64 column-major fine blocks of leading
+// dimension ldf) and round to TF.
 template <class TF>
-hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s);
+hipError_t launch_extract_sub(const double* fine, int nbf, int ldf, int nvf, int nvc, TF* out, int nblk,
+                              hipStream_t s);
 // Block-sparse product y = K x with 7 blocks per element row (diagonal + 6
 // faces), stored sliced row-major: rows padded to bsr_ldr(nbc) entries per
 // block, grouped by 64 rows, 16-byte chunks of a group contiguous.  With

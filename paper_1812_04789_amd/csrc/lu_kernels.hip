@@ -135,23 +135,26 @@ template hipError_t launch_lu_solve<float>(const float*, const int*, const doubl
 // Coarse principal sub-block: rows/columns (a, i), i < nvc, of the fine block
 // whose local index is a*nvf + i; output local index a*nvc + i.
 template <class TF>
-__global__ void extract_sub_kernel(const double* __restrict__ fine, int nbf, int nvf, int nvc, TF* __restrict__ out) {
+__global__ void extract_sub_kernel(const double* __restrict__ fine, int nbf, int ldf, int nvf, int nvc,
+                                   TF* __restrict__ out) {
     const int nbc = 5 * nvc;
-    const double* fb = fine + (size_t)blockIdx.x * nbf * nbf;
+    const double* fb = fine + (size_t)blockIdx.x * nbf * ldf;
     TF* ob = out + (size_t)blockIdx.x * nbc * nbc;
     for (int idx = threadIdx.x; idx < nbc * nbc; idx += blockDim.x) {
         const int jc = idx / nbc, ic = idx % nbc;
         const int jf = (jc / nvc) * nvf + jc % nvc, i_f = (ic / nvc) * nvf + ic % nvc;
-        ob[idx] = (TF)fb[(size_t)jf * nbf + i_f];
+        ob[idx] = (TF)fb[(size_t)jf * ldf + i_f];
     }
 }
 template <class TF>
-hipError_t launch_extract_sub(const double* fine, int nbf, int nvf, int nvc, TF* out, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(extract_sub_kernel<TF>, dim3(nblk), dim3(256), 0, s, fine, nbf, nvf, nvc, out);
+hipError_t launch_extract_sub(const double* fine, int nbf, int ldf, int nvf, int nvc, TF* out, int nblk,
+                              hipStream_t s) {
+    if (ldf < nbf) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(extract_sub_kernel<TF>, dim3(nblk), dim3(256), 0, s, fine, nbf, ldf, nvf, nvc, out);
     return hipGetLastError();
 }
-template hipError_t launch_extract_sub<double>(const double*, int, int, int, double*, int, hipStream_t);
-template hipError_t launch_extract_sub<float>(const double*, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_extract_sub<double>(const double*, int, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_extract_sub<float>(const double*, int, int, int, int, float*, int, hipStream_t);
 
 // ---- blocked variants used by the smoother -------------------------------------------------
 // Right-looking PLU with column panels.  The panel (rows k0..n-1) is factored
@@ -199,8 +202,8 @@ __device__ __forceinline__ int block_argmax(TA v, int r, TA* sv, int* sr) {
 // columns enter as zeros and are not stored.
 constexpr int UPD_G = 2;
 template <class TF, class TA, int NBW>
-__device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const TA* P, int n, int k0, int kb, int n2,
-                                                     int t) {
+__device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const TA* P, int n, int ld, int k0, int kb,
+                                                     int n2, int t) {
     typedef TA acc4 __attribute__((ext_vector_type(4)));
     static_assert(NBW % 4 == 0, "the panel width is a multiple of the instruction's K = 4");
     static_assert(LU_THREADS % 64 == 0, "whole wavefronts");
@@ -208,12 +211,12 @@ __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const T
     const int lane = t & 63, wv = t >> 6, nwv = LU_THREADS / 64;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = (n2 + 15) / 16;
-    TF* a22 = a + (size_t)(k0 + kb) * n + k0 + kb;          // A22[r][c] = a22[c n + r]
+    TF* a22 = a + (size_t)(k0 + kb) * ld + k0 + kb;         // A22[r][c] = a22[c ld + r]
     const TA* l21 = P + kb;                                  // L21[r][k] = l21[k n + r]
     for (int st = wv; st < nt; st += nwv) {
         const int c0 = st * 16;
         const bool cok = c0 + li < n2;
-        const TF* ucol = a + (size_t)(k0 + kb + (cok ? c0 + li : 0)) * n + k0;
+        const TF* ucol = a + (size_t)(k0 + kb + (cok ? c0 + li : 0)) * ld + k0;
         TA uv[NK];
 #pragma unroll
         for (int q = 0; q < NK; ++q) {
@@ -230,7 +233,7 @@ __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const T
                 const int r = r0 + 16 * g + li;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    acc[g][i] = (r < n2 && cc[i] < n2) ? (TA)a22[(size_t)cc[i] * n + r] : TA(0);
+                    acc[g][i] = (r < n2 && cc[i] < n2) ? (TA)a22[(size_t)cc[i] * ld + r] : TA(0);
             }
 #pragma unroll
             for (int g = 0; g < UPD_G; ++g) {
@@ -250,7 +253,7 @@ __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const T
                 const int r = r0 + 16 * g + li;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (r < n2 && cc[i] < n2) a22[(size_t)cc[i] * n + r] = (TF)acc[g][i];
+                    if (r < n2 && cc[i] < n2) a22[(size_t)cc[i] * ld + r] = (TF)acc[g][i];
             }
         }
     }
@@ -261,7 +264,8 @@ __device__ __forceinline__ void trailing_update_mfma(TF* __restrict__ a, const T
 // 16 columns; FP32 blocks: float arithmetic, 32 columns (the same 40 KB panel,
 // half the trailing-matrix passes).
 template <class TF, class TA, int NBW>
-__global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n) {
+__global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__ A, int* __restrict__ piv, int n,
+                                                                int ld) {
     extern __shared__ double lds_raw[];
     TA* P = reinterpret_cast<TA*>(lds_raw);  // panel, column-major with stride n: P[c*n + r], r < m
     __shared__ TA wv[LU_THREADS / 64];
@@ -270,7 +274,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
     // perm[r]: the row (relative to k0) whose content row r holds after the
     // panel's exchanges so far
     int* perm = reinterpret_cast<int*>(P + (size_t)NBW * n);
-    TF* a = A + (size_t)blockIdx.x * n * n;
+    TF* a = A + (size_t)blockIdx.x * n * ld;                 // column c at a + c ld
     int* pv = piv + (size_t)blockIdx.x * n;
     const int t = threadIdx.x;
     for (int k0 = 0; k0 < n; k0 += NBW) {
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         for (int r = t; r < m; r += LU_THREADS) perm[r] = r;
         for (int idx = t; idx < m * kb; idx += LU_THREADS) {
             const int c = idx / m, r = idx % m;
-            P[c * n + r] = (TA)a[(size_t)(k0 + c) * n + k0 + r];
+            P[c * n + r] = (TA)a[(size_t)(k0 + c) * ld + k0 + r];
         }
         __syncthreads();
         for (int j = 0; j < kb; ++j) {
@@ -314,7 +318,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         // panel back to memory (rounded to the storage type)
         for (int idx = t; idx < m * kb; idx += LU_THREADS) {
             const int c = idx / m, r = idx % m;
-            a[(size_t)(k0 + c) * n + k0 + r] = (TF)P[c * n + r];
+            a[(size_t)(k0 + c) * ld + k0 + r] = (TF)P[c * n + r];
         }
         // every other column: the panel's row exchanges at once (rows 0..kb-1
         // and the pivot rows change; each column's reads come before its
@@ -345,7 +349,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
                 for (int u = 0; u < CPI; ++u) {
                     const int cr = c0 + u * NG;
                     const int c = (cr < k0) ? cr : cr + kb;
-                    cols[u] = a + (size_t)(cr < ncol ? c : 0) * n + k0;
+                    cols[u] = a + (size_t)(cr < ncol ? c : 0) * ld + k0;
                     y[u] = (cr < ncol && rowok) ? cols[u][ysrc] : TF(0);
                     z[u] = (cr < ncol && zon) ? cols[u][zsrc] : TF(0);
                 }
@@ -373,7 +377,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_blocked_kernel(TF* __restrict__
         if (n2 <= 0) break;
         // A22 -= L21 U12 on the matrix cores: 16 x 16 tiles of A22, one per
         // wavefront at a time, K = 4 per instruction over the panel width
-        trailing_update_mfma<TF, TA, NBW>(a, P, n, k0, kb, n2, t);
+        trailing_update_mfma<TF, TA, NBW>(a, P, n, ld, k0, kb, n2, t);
         __syncthreads();
     }
 }
@@ -404,21 +408,22 @@ template <> struct LuCfg<double> { using TA = double; static constexpr int NBW =
 template <> struct LuCfg<float> { using TA = float; static constexpr int NBW = 32; };
 
 template <class TF>
-hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, hipStream_t s) {
+hipError_t launch_lu_blocked(TF* A, int* piv, int* pos, int nblk, int n, int ld, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
+    if (ld < n) return hipErrorInvalidValue;
     using C = LuCfg<TF>;
     const size_t lds = (size_t)C::NBW * n * sizeof(typename C::TA) + (size_t)n * sizeof(int);
     auto kern = lu_blocked_kernel<TF, typename C::TA, C::NBW>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(LU_THREADS), lds, s, A, piv, n);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(LU_THREADS), lds, s, A, piv, n, ld);
     e = hipGetLastError();
     if (e != hipSuccess || !pos) return e;
     hipLaunchKernelGGL(lu_pos_kernel, dim3(nblk), dim3(256), n * sizeof(int), s, piv, pos, n);
     return hipGetLastError();
 }
-template hipError_t launch_lu_blocked<double>(double*, int*, int*, int, int, hipStream_t);
-template hipError_t launch_lu_blocked<float>(float*, int*, int*, int, int, hipStream_t);
+template hipError_t launch_lu_blocked<double>(double*, int*, int*, int, int, int, hipStream_t);
+template hipError_t launch_lu_blocked<float>(float*, int*, int*, int, int, int, hipStream_t);
 
 // ---- explicit block inverse for the smoother apply --------------------------------------------
 // X = A^-1 from the PLU factors: X starts as P I (X[c][i] = 1 iff pos[i] = c)
