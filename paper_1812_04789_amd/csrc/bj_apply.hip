@@ -44,12 +44,43 @@ __device__ __forceinline__ TF tri_load(const TF* __restrict__ a, size_t idx, boo
 
 // x[row] -= sum_{j < kb} a[(k0 + j) ld + row] x[k0 + j] for rows [r0, r1): the
 // panel's factor entries of a row, all loads of a lane in flight at once.
-// FP32 factors with an even leading dimension take two rows per lane
-// (8-byte loads, half the load instructions for the same bytes).
+// FP32 factors take four rows per lane when the leading dimension is a
+// multiple of 4 (16-byte loads, the panel's columns in two halves of 16),
+// else two rows when it is even (8-byte loads): fewer load instructions for
+// the same bytes.  Rows past r1 that such a load covers lie inside the
+// column (ld >= n) and are never used.
 template <class TF>
 __device__ __forceinline__ void panel_rows(const TF* __restrict__ a, int ld, int k0, int kb, int r0, int r1,
                                            double* x, int t) {
     if constexpr (sizeof(TF) == 4) {
+        if ((ld & 3) == 0 && (r0 & 3) == 0) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            for (int row = r0 + 4 * t; row < r1; row += 4 * SOLVE_THREADS) {
+                double acc[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = (row + u < r1) ? x[row + u] : 0.0;
+#pragma unroll
+                for (int h = 0; h < TS; h += 16) {
+                    f4v av[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+                        av[j] = ld_stream(reinterpret_cast<const f4v*>(&a[(size_t)(k0 + (h + j < kb ? h + j : 0)) * ld + row]));
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+                        if (h + j < kb) {
+                            const double xj = x[k0 + h + j];
+                            acc[0] -= (double)av[j].x * xj;
+                            acc[1] -= (double)av[j].y * xj;
+                            acc[2] -= (double)av[j].z * xj;
+                            acc[3] -= (double)av[j].w * xj;
+                        }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (row + u < r1) x[row + u] = acc[u];
+            }
+            return;
+        }
         // (with r1 odd the last pair's second row lies in the column's
         // padding, ld > n: loaded, never used)
         if ((ld & 1) == 0 && (r0 & 1) == 0) {
