@@ -173,12 +173,24 @@ dg_status dg_mass(dg_ctx* ctx, const double* v, double* y);
 dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* blocks);
 
 /* Face-coupling blocks of the inherited coarse operator of degree pc
- * (Sec. 6.1, K_l = P^T K_0 P; 1 <= pc < p): off [ne][6][nbc][nbc], nbc =
+ * (Sec. 6.1, K_l = P^T K_0 P; 1 <= pc <= p, pc = p giving the face blocks of
+ * the fine operator itself): off [ne][6][nbc][nbc], nbc =
  * 5 (pc+1)^3, column-major, off[e][f][j][i] = dR_{e,i}/dW_{nb(e,f),j} through
  * the integral over face f only (i, j equation-major over the modes of
  * degree <= pc).  A face whose neighbour is the element itself gives a zero
  * block (that coupling is part of the diagonal block). */
 dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off);
+
+/* Matrix-based product (the assembled alternative to Eq. DG-mf that Sec. 5
+ * compares against the matrix-free form): dg_assemble_operator stores
+ * K = shift M + dR/dW at W, every element's diagonal block and its six
+ * face-coupling blocks (7 nb^2 FP64 entries per element, held by the context
+ * until the next call or dg_destroy; 23.5 GB at 16^3, p = 3), and
+ * dg_jvp_assembled computes y = K v with it.  Both enqueue on the context's
+ * stream; v and y are device [ne][5][nv], y must not alias v.
+ * dg_jvp_assembled before dg_assemble_operator: DG_ESTATE. */
+dg_status dg_assemble_operator(dg_ctx* ctx, const double* W, double shift);
+dg_status dg_jvp_assembled(dg_ctx* ctx, const double* v, double* y);
 
 /* Batched PLU with partial pivoting (Sec. 6.3), in place, LAPACK convention
  * (column-major blocks, rows k and piv[k] exchanged at step k, unit-lower L

@@ -103,6 +103,8 @@ SIGNATURES = {
     "dg_mass": (_I, [_P, _P, _P]),
     "dg_assemble_diag": (_I, [_P, _P, _D, _P]),
     "dg_assemble_coarse": (_I, [_P, _P, _I, _P]),
+    "dg_assemble_operator": (_I, [_P, _P, _D]),
+    "dg_jvp_assembled": (_I, [_P, _P, _P]),
     "dg_batched_lu": (_I, [_P, _P, _P, _I, _I]),
     "dg_batched_lu_solve": (_I, [_P, _P, _P, _P, _P, _I, _I]),
     "pmg_setup": (_I, [_P, _P, _D, ctypes.POINTER(PmgOpts)]),
@@ -328,6 +330,16 @@ class Context:
         out = self.empty(self.ne * 6 * nbc * nbc)
         self._check(self.lib.dg_assemble_coarse(self.h, self._vec(W, "W"), int(pc), _ptr(out)))
         return out.view(self.ne, 6, nbc, nbc)     # [e][f][col][row]
+
+    def assemble_operator(self, W, shift):
+        """Store K = shift M + dR/dW at W in the context (7 FP64 blocks per element)."""
+        self._check(self.lib.dg_assemble_operator(self.h, self._vec(W, "W"), float(shift)))
+
+    def jvp_assembled(self, v, y=None):
+        """y = K v with the operator of the last assemble_operator call."""
+        y = self.empty() if y is None else y
+        self._check(self.lib.dg_jvp_assembled(self.h, self._vec(v, "v"), self._vec(y, "y")))
+        return y
 
     def pmg_setup(self, W, shift, opts):
         self._check(self.lib.pmg_setup(self.h, self._vec(W, "W"), float(shift), ctypes.byref(opts)))

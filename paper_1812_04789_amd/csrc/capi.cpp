@@ -121,6 +121,8 @@ struct dg_ctx {
     DBuf<double> partial, scal;
     DBuf<int> flag;
     DBuf<double> tmp1, tmp2, tmp3;          // N-vector scratch for jvp / pMG / Newton
+    DBuf<double> mb_op;                     // assembled fine operator (7-block BSR rows), dg_assemble_operator
+    bool mb_ready = false;
     // preconditioner
     bool pmg_ready = false;
     pmg_opts popt{};
@@ -918,6 +920,7 @@ dg_status dg_destroy(dg_ctx* ctx) {
     ctx->vtx.release(); ctx->partial.release(); ctx->scal.release(); ctx->flag.release();
     ctx->tmp1.release(); ctx->tmp2.release(); ctx->tmp3.release();
     ctx->W0.release(); ctx->RW0.release(); ctx->blk.release(); ctx->otmp.release(); ctx->dtmp.release(); ctx->nbrtr.release();
+    ctx->mb_op.release();
     for (auto& L : ctx->lv) L.release();
     ctx->kc.release(); ctx->kf.release();
     ctx->RW.release(); ctx->Ru.release(); ctx->xN.release();
@@ -1002,8 +1005,34 @@ dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off) 
     return guarded(ctx, [&] {
         need(ctx, W, "W");
         need(ctx, off, "off");
-        if (pc < 1 || pc >= ctx->p) fail(ctx, DG_EINVAL, "pc must satisfy 1 <= pc < p");
+        if (pc < 1 || pc > ctx->p) fail(ctx, DG_EINVAL, "pc must satisfy 1 <= pc <= p");
         CK(launch_offdiag_blocks(ctx->a, W, pc, off, ctx->s));
+    });
+}
+
+dg_status dg_assemble_operator(dg_ctx* ctx, const double* W, double shift) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        ctx->mb_ready = false;
+        const size_t sz = (size_t)ctx->ne * ctx->nb * ctx->nb;
+        ctx->dtmp.ensure(sz);
+        ctx->otmp.ensure(6 * sz);
+        ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
+        CK(launch_diag_blocks(ctx->a, W, shift, ctx->dtmp.p, ctx->nb, ctx->nbrtr.p, ctx->s));
+        CK(launch_offdiag_blocks(ctx->a, W, ctx->p, ctx->otmp.p, ctx->s));
+        ctx->mb_op.ensure(bsr_entries(ctx->ne, ctx->nb, 7));
+        CK(launch_bsr_pack<double>(ctx->dtmp.p, ctx->otmp.p, ctx->mb_op.p, ctx->ne, ctx->nb, 7, ctx->s));
+        ctx->mb_ready = true;
+    });
+}
+
+dg_status dg_jvp_assembled(dg_ctx* ctx, const double* v, double* y) {
+    return guarded(ctx, [&] {
+        if (!ctx->mb_ready) fail(ctx, DG_ESTATE, "dg_assemble_operator has not been called");
+        need(ctx, v, "v");
+        need(ctx, y, "y");
+        if (v == y) fail(ctx, DG_EINVAL, "y must not alias v");
+        CK(launch_bsr7<double>(ctx->a, ctx->mb_op.p, v, y, ctx->nb, ctx->s));
     });
 }
 

@@ -1465,6 +1465,11 @@ hipError_t launch_offdiag_blocks(const DGArgs& a, const double* W, int pc, doubl
         case 41: return launch_offdiag_pc<4, 1>(a, W, out, s);
         case 42: return launch_offdiag_pc<4, 2>(a, W, out, s);
         case 43: return launch_offdiag_pc<4, 3>(a, W, out, s);
+        // pc = p: the face-coupling blocks of the fine operator itself
+        case 11: return launch_offdiag_pc<1, 1>(a, W, out, s);
+        case 22: return launch_offdiag_pc<2, 2>(a, W, out, s);
+        case 33: return launch_offdiag_pc<3, 3>(a, W, out, s);
+        case 44: return launch_offdiag_pc<4, 4>(a, W, out, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1634,6 +1639,11 @@ hipError_t launch_bsr7(const DGArgs& a, const SF* A, const double* x, double* y,
     const size_t nrows = (size_t)a.m.ne * nbc;
     const unsigned grid = (unsigned)((nrows + 255) / 256);
     const size_t lds = (size_t)(256 / nbc + 2) * 7 * bsr_ldr(nbc) * sizeof(AT);
+    if (lds > 65536) {      // fine-order blocks (nbc = 625): the gathered neighbour values exceed 64 KB
+        const hipError_t e = hipFuncSetAttribute((const void*)bsr_rows_kernel<SF, AT, false>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((bsr_rows_kernel<SF, AT, false>), dim3(grid), dim3(256), lds, s, a.m, nbc, A, x, y);
     return hipGetLastError();
 }
