@@ -168,6 +168,8 @@ def run(args):
                          hbm_frac=32.0 * ctx.ndof / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
     if args.workload == "tgv_p3_16" and not args.no_large_jvp:
         jv["fd_32cube"] = large_jvp()
+    if not args.no_matrix_based:
+        jv["matrix_based"] = matrix_based_jvp(wl)
 
     # ---- mixed precision steps (FP32 fine factors, BF16 coarse operators) -------------
     mixed = None
@@ -260,6 +262,39 @@ def large_jvp():
     out = dict(ndof=c.ndof, kernel_ms=kms, gdof_s=c.ndof / (kms * 1e-3) / 1e9,
                kernel_gbs=32.0 * c.ndof / (kms * 1e-3) / 1e9,
                hbm_frac=32.0 * c.ndof / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    c.close()
+    return out
+
+
+def matrix_based_jvp(wl):
+    """The matrix-based alternative to Eq. DG-mf on the benchmark mesh: K =
+    shift M + dR/dW assembled once (diagonal + six face blocks per element,
+    FP64) and applied by the 7-block product; call time over 5 products, in a
+    context of its own so its ~47 GB are released afterwards."""
+    import torch
+    from paper_1812_04789_amd import binding, inputs
+    c = binding.Context(wl["n"], wl["lo"], wl["hi"], wl["p"], gamma=1.4, mu=wl["mu"], Pr=wl["Pr"], eta=7.0)
+    W = c.project(torch.tensor(inputs.taylor_green(c.quad_points().cpu().numpy(), mach=wl["mach"]).reshape(-1),
+                               device="cuda"))
+    v = torch.tensor(inputs.random_vector(c.ne, c.p, seed=7).reshape(-1), device="cuda")
+    t0 = time.perf_counter()
+    c.assemble_operator(W, 30.0)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    y = c.empty()
+    c.jvp_assembled(v, y)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(5):
+        c.jvp_assembled(v, y)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    nb = 5 * c.nv
+    by = c.ne * (7.0 * nb * nb * 8 + 16.0 * nb)
+    out = dict(assemble_s=t_asm, call_ms=ms, gdof_s=c.ndof / (ms * 1e-3) / 1e9, gbs=by / (ms * 1e-3) / 1e9,
+               hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, operator_gb=by / 1e9)
     c.close()
     return out
 
@@ -408,6 +443,7 @@ def main():
     ap.add_argument("--workload", default="tgv_p3_16", choices=sorted(WORKLOADS))
     ap.add_argument("--jvp-reps", type=int, default=30)
     ap.add_argument("--no-large-jvp", action="store_true", help="skip the 32^3 p=3 FD product")
+    ap.add_argument("--no-matrix-based", action="store_true", help="skip the assembled-operator product")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
