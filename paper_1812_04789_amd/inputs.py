@@ -28,14 +28,16 @@ import numpy as np
 
 
 # ---- meshes -----------------------------------------------------------------
-def box_vertices(n, lo, hi, amp=0.0):
+def box_vertices(n, lo, hi, amp=0.0, phase=0.0):
     """Vertex table (ne, 8, 3) of a periodic box of n = (nx,ny,nz) hexahedra.
 
     Local vertex v = i + 2j + 4k of element (I,J,K) is grid node
     (I+i, J+j, K+k).  With amp != 0 every node is displaced by
-    amp * h * sin(x) sin(y) sin(z) in each coordinate (h = the x spacing),
-    evaluated at the node's position wrapped into the box so that the copies of
-    a node seen across a periodic boundary differ by exactly one period."""
+    amp * h * sin(x+phase) sin(y+phase) sin(z+phase) in each coordinate
+    (h = the x spacing), evaluated at the node's position wrapped into the box
+    so that the copies of a node seen across a periodic boundary differ by
+    exactly one period.  (With phase = 0 the nodes of a 2-element-wide
+    [0, 2pi] axis sit where sin vanishes and do not move.)"""
     nx, ny, nz = (int(x) for x in n)
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
@@ -51,7 +53,7 @@ def box_vertices(n, lo, hi, amp=0.0):
                     nn = np.array([nx, ny, nz])
                     wrap = g % nn
                     base = lo + h * wrap
-                    disp = amp * h[0] * math.sin(base[0]) * math.sin(base[1]) * math.sin(base[2])
+                    disp = amp * h[0] * math.sin(base[0] + phase) * math.sin(base[1] + phase) * math.sin(base[2] + phase)
                     V[e, v] = base + disp + L * (g // nn)
     return V
 

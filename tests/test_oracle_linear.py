@@ -209,3 +209,58 @@ def test_bdf2_newton_step_conserves_and_converges():
     U[:, :, 0] = np.array([1.0, 0.1, 0.2, -0.1, 2.5]) * inputs.MODE0_SCALE
     U1, st = ts.bdf2_step(D, U, None, 0.1, precond="bj")
     assert st.newton == 0 and np.array_equal(U1, U)
+
+
+class _LinearDecay:
+    """Stub discretisation R(W) = lam M W with a fixed symmetric positive
+    definite block mass matrix M (complex-safe), for pinning the time scheme
+    on its own."""
+
+    def __init__(self, ne=3, nv=8, lam=0.7, seed=0):
+        rng = np.random.default_rng(seed)
+        A = rng.standard_normal((ne, nv, nv))
+        self.M = np.einsum('eij,ekj->eik', A, A) + nv * np.eye(nv)
+        self.lam = lam
+
+    def mass(self, v):
+        return np.einsum('eij,eaj->eai', self.M, v)
+
+    def residual(self, W):
+        return self.lam * self.mass(W)
+
+
+def test_bdf2_step_closed_form_with_history():
+    """Sec. 4, Eq. NEWTON with the BDF2 coefficients: for R(W) = lam M W the
+    step M(3W - 4W^n + W^{n-1})/(2 dt) + lam M W = 0 has the closed form
+    W = (4W^n - W^{n-1}) / (3 + 2 dt lam), here with W^{n-1} != W^n.  Backward
+    Euler (W = W^n / (1 + dt lam)) or a dropped history term fails it."""
+    D = _LinearDecay()
+    rng = np.random.default_rng(1)
+    Wn = rng.standard_normal((3, 5, 8))
+    Wnm1 = Wn + 0.3 * rng.standard_normal(Wn.shape)
+    dt = 0.4
+    W1, st = ts.bdf2_step(D, Wn, Wnm1, dt, precond=None, restart=60, rtol=1e-13, newton_tol=1e-12)
+    ref = (4 * Wn - Wnm1) / (3 + 2 * dt * D.lam)
+    assert st.newton >= 1
+    assert np.allclose(W1, ref, rtol=1e-11, atol=1e-12)
+    assert not np.allclose(W1, Wn / (1 + dt * D.lam), rtol=1e-3)
+
+
+def test_bdf2_is_second_order_in_time():
+    """Repeated steps of the stub integrate dW/dt = -lam W with global error
+    O(dt^2): halving dt divides the error at t = 1 by about 4.  The history
+    of the first step is the exact solution at t = -dt (starting from
+    W^{n-1} = W^n instead is an O(dt) perturbation that caps the global
+    rate at one)."""
+    D = _LinearDecay(lam=1.3)
+    W0 = np.random.default_rng(2).standard_normal((3, 5, 8))
+    errs = []
+    for nsteps in (10, 20, 40):
+        dt = 1.0 / nsteps
+        Wnm1, Wn = W0 * math.exp(D.lam * dt), W0
+        for k in range(nsteps):
+            W1, _ = ts.bdf2_step(D, Wn, Wnm1, dt, precond=None, restart=60, rtol=1e-13, newton_tol=1e-12)
+            Wnm1, Wn = Wn, W1
+        errs.append(np.abs(Wn - W0 * math.exp(-D.lam)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.8, (errs, rates)

@@ -1,7 +1,8 @@
 """Pins of the oracle's DG residual (CPU only): Sec. 3.1, Eqs. dg_ns,
 visc_flux, re.  Free stream, discrete conservation, the BR2 lifting in closed
 form, adjoint consistency (symmetry), periodic equivariance and the order of
-accuracy on an exact Euler solution."""
+accuracy on an exact Euler solution; the BR2 penalty makes the viscous
+operator semi-definite (indefinite without it)."""
 import math
 
 import numpy as np
@@ -111,6 +112,41 @@ def test_br2_adjoint_consistency_symmetry():
     D.symmetry_term = False
     A2 = _dense_jacobian(D, W)[np.ix_(idx, idx)]
     assert np.abs(A2 - A2.T).max() > 1e-2 * np.abs(A2).max()
+
+
+@pytest.mark.parametrize("n,amp", [((2, 2, 2), 0.0), ((3, 2, 2), 0.2)])
+def test_br2_penalty_makes_the_viscous_operator_semidefinite(n, amp):
+    """The BR2 viscous operator is the discretisation of a symmetric positive
+    semi-definite form (int grad w : K grad u for the momentum equations under
+    the Stokes hypothesis and for the energy equation, linearised about a
+    uniform rest state with F_c off), provided the penalty eta_F is large
+    enough (Sec. 3.1, Eq. visc_flux: eta_F above the number of faces).  With
+    eta_F = 7 the momentum-momentum and energy-energy blocks of dR/dW are
+    symmetric positive semi-definite; with the penalty term negated or
+    removed they are indefinite (many negative eigenvalues of size comparable
+    to the positive ones)."""
+    m = _mesh(n, amp > 0, amp=amp)
+    W = np.zeros((m.ne, 5, (1 + 1) ** 3))
+    W[:, :, 0] = np.array([1.0, 0.0, 0.0, 0.0, 3.0]) * inputs.MODE0_SCALE
+
+    def blocks(eta):
+        D = dg.Discretization(m, 1, mu=0.1, Pr=0.71, eta=eta)
+        D.inviscid = False
+        J = _dense_jacobian(D, W)
+        out = []
+        for eqs in ((1, 2, 3), (4,)):
+            idx = np.array([e * 5 * D.nv + a * D.nv + i for e in range(m.ne) for a in eqs for i in range(D.nv)])
+            out.append(J[np.ix_(idx, idx)])
+        return out
+
+    for B in blocks(7.0):
+        assert np.abs(B - B.T).max() < 1e-12 * np.abs(B).max()
+        ev = np.linalg.eigvalsh(0.5 * (B + B.T))
+        assert ev.max() > 0.0 and ev.min() > -1e-12 * ev.max()
+    for eta in (-7.0, 0.0):
+        for B in blocks(eta):
+            ev = np.linalg.eigvalsh(0.5 * (B + B.T))
+            assert ev.min() < -0.2 * ev.max(), (eta, ev.min(), ev.max())
 
 
 def test_periodic_shift_equivariance():
