@@ -47,15 +47,11 @@ WORKLOADS = {
 }
 
 
-def run(args):
-    import numpy as np
+def make_case(wl_name):
+    """Context and projected initial state of a workload."""
     import torch
     from paper_1812_04789_amd import binding, inputs
-
-    wl = WORKLOADS[args.workload]
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        calibrate_copy()
+    wl = WORKLOADS[wl_name]
     vtx = inputs.box_vertices(wl["n"], wl["lo"], wl["hi"], amp=wl["curved"]) if wl["curved"] else None
     ctx = binding.Context(wl["n"], wl["lo"], wl["hi"], wl["p"], gamma=1.4, mu=wl["mu"], Pr=wl["Pr"], eta=7.0,
                           vertices=vtx)
@@ -67,17 +63,28 @@ def run(args):
     W0 = ctx.project(torch.tensor(vals.reshape(-1), device="cuda"))
     if wl["ic"] == "vortex":
         W0 += torch.tensor(inputs.uniform_noise((ctx.ne, 5, ctx.nv), 1812, 1e-6).reshape(-1), device="cuda")
+    return wl, ctx, W0
+
+
+def popts_for(wl, mixed, coarse):
+    from paper_1812_04789_amd import binding
+    if mixed:
+        return binding.pmg_opts(wl["levels"], prec_fine=binding.DG_FP32, prec_coarse=binding.DG_BF16,
+                                coarse_matrix_free=coarse)
+    return binding.pmg_opts(wl["levels"], prec_fine=binding.DG_FP64, prec_coarse=binding.DG_FP64,
+                            coarse_matrix_free=coarse)
+
+
+def time_steps(wl, ctx, W0, popts, nsteps, warmup):
+    """`warmup` untimed then `nsteps` timed consecutive BDF2 steps from W0 (the
+    first step of each run takes W^{n-1} = W^n); returns (seconds per step,
+    final state, per-step statistics)."""
+    import torch
+    from paper_1812_04789_amd import binding
     fopts = binding.fgmres_opts(restart=wl["restart"], rtol=wl["rtol"])
 
-    def popts_for(mixed):
-        if mixed:
-            return binding.pmg_opts(wl["levels"], prec_fine=binding.DG_FP32, prec_coarse=binding.DG_BF16,
-                                    coarse_matrix_free=args.coarse)
-        return binding.pmg_opts(wl["levels"], prec_fine=binding.DG_FP64, prec_coarse=binding.DG_FP64,
-                                coarse_matrix_free=args.coarse)
-
-    def steps(popts, K, W):
-        Wn, Wnm1 = W.clone(), None
+    def run_steps(K):
+        Wn, Wnm1 = W0.clone(), None
         stats = []
         for _ in range(K):
             Wnp1, st = ctx.bdf2_step(Wn, Wnm1, wl["dt"], popts, fopts, newton_rtol=wl.get("newton_rtol", 1e-10))
@@ -85,24 +92,23 @@ def run(args):
             Wnm1, Wn = Wn, Wnp1
         return Wn, stats
 
-    # ---- FP64 timed steps (production path: V-cycles replayed as HIP graphs) ------
-    popts64 = popts_for(False)
-    steps(popts64, args.warmup, W0)
+    if warmup:
+        run_steps(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    W64, st64 = steps(popts64, args.steps, W0)
+    W, st = run_steps(nsteps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    value = ctx.ndof * args.steps / elapsed / 1e9
-    # the same first step again with every kernel family bracketed by HIP events
+    return (time.perf_counter() - t0) / nsteps, W, st
+
+
+def kernel_families(ctx, wl, W0, popts):
+    """Per-family device time of one instrumented step (HIP events on the
+    library stream, eager launches), with the library's algorithmic bytes and
+    flops per launch."""
     ctx.timing(True)
-    steps(popts64, 1, W0)
+    time_steps(wl, ctx, W0, popts, 1, 0)
     kern = ctx.timing_read()
     ctx.timing(False)
-
-    # ---- kernel roofline (families measured live over the timed steps) -------------
-    # Algorithmic bytes / flops per launch come from the library (dg_timing_read).
     fams = {}
     for kind, (ms, cnt, by, fl) in kern.items():
         if cnt == 0:
@@ -110,21 +116,42 @@ def run(args):
         fams[kind] = dict(ms_total=ms, launches=cnt, ms_avg=ms / cnt, bytes_per_launch=by / cnt,
                           gbs=(by / (ms * 1e-3) / 1e9) if (by and ms > 0) else None,
                           tflops=(fl / (ms * 1e-3) / 1e12) if (fl and ms > 0) else None)
-    dom = max(fams, key=lambda k: fams[k]["ms_total"]) if fams else None
-    roof = None
-    if dom:
-        f = fams[dom]
-        kname = kernel_name(dom, ctx.p, popts64)
-        if dom in ("lu", "diag_blocks"):
-            roof = dict(kernel=kname, family=dom, bound="alu", achieved=f["tflops"], peak=FP64_PEAK_TFS,
-                        unit="TFLOP/s", frac=(f["tflops"] or 0.0) / FP64_PEAK_TFS, traffic=None,
-                        ms_avg=f["ms_avg"])
-        else:
-            roof = dict(kernel=kname, family=dom, bound="hbm", achieved=f["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=f["gbs"] / HBM_PEAK_GBS, traffic=measured_traffic(kname, args.workload),
-                        ms_avg=f["ms_avg"], bytes_per_launch=f["bytes_per_launch"])
+    return fams
 
-    # ---- J.v throughput (the paper's FD product and the exact product) --------------
+
+def step_summary(wl, ctx, W0, nsteps, warmup, coarse):
+    """FP64 and mixed-precision steps of one workload: seconds per step, the
+    speed-up, solver statistics and the distance between the two solutions."""
+    t64, W64, st64 = time_steps(wl, ctx, W0, popts_for(wl, False, coarse), nsteps, warmup)
+    out = {"fp64": t64, "newton": [s_.newton for s_ in st64], "fgmres_iters": [s_.linear_iters for s_ in st64],
+           "max_rel_res_true": max(s_.max_rel_res_true for s_ in st64),
+           "setup_s": float(sum(s_.setup_seconds for s_ in st64) / len(st64))}
+    if len(wl["levels"]) > 1 or wl["p"] > 1:
+        t32, W32, st32 = time_steps(wl, ctx, W0, popts_for(wl, True, coarse), nsteps, min(warmup, 1))
+        out.update({"mixed": t32, "speedup": t64 / t32,
+                    "mixed_newton": [s_.newton for s_ in st32],
+                    "mixed_fgmres_iters": [s_.linear_iters for s_ in st32],
+                    "mixed_max_rel_res_true": max(s_.max_rel_res_true for s_ in st32),
+                    "mixed_vs_fp64_rel": (W32 - W64).norm().item() / W64.norm().item()})
+    return out
+
+
+def roofline_of(fams, dom, ctx, popts, workload):
+    f = fams[dom]
+    kname = kernel_name(dom, ctx.p, popts)
+    if dom in ("lu", "diag_blocks"):
+        return dict(kernel=kname, family=dom, bound="alu", achieved=f["tflops"], peak=FP64_PEAK_TFS,
+                    unit="TFLOP/s", frac=(f["tflops"] or 0.0) / FP64_PEAK_TFS, traffic=None, ms_avg=f["ms_avg"])
+    return dict(kernel=kname, family=dom, bound="hbm", achieved=f["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=f["gbs"] / HBM_PEAK_GBS, traffic=measured_traffic(kname, workload),
+                ms_avg=f["ms_avg"], bytes_per_launch=f["bytes_per_launch"])
+
+
+def jvp_rates(ctx, W0, reps):
+    """FD product of Eq. DG-mf, exact product and residual: call time (HIP
+    events around `reps` calls) and kernel time (the library's events)."""
+    import torch
+    from paper_1812_04789_amd import inputs
     v = torch.tensor(inputs.random_vector(ctx.ne, ctx.p, seed=7).reshape(-1), device="cuda")
     RW = ctx.residual(W0)
     y = ctx.empty()
@@ -137,7 +164,7 @@ def run(args):
         ctx.timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        for _ in range(args.jvp_reps):
+        for _ in range(reps):
             fn()
         e1.record(s)
         e1.synchronize()
@@ -145,12 +172,11 @@ def run(args):
         ctx.timing(False)
         kname = {"fd": "jvp_fd", "exact": "jvp_exact", "residual": "residual"}[name]
         kms, kc = kk[kname][0], kk[kname][1]
-        jv[name] = dict(call_ms=e0.elapsed_time(e1) / args.jvp_reps, kernel_ms=kms / max(kc, 1),
-                        gdof_s=ctx.ndof / (e0.elapsed_time(e1) / args.jvp_reps * 1e-3) / 1e9)
+        jv[name] = dict(call_ms=e0.elapsed_time(e1) / reps, kernel_ms=kms / max(kc, 1),
+                        gdof_s=ctx.ndof / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9)
         by = {"fd": 32.0, "exact": 24.0, "residual": 16.0}[name] * ctx.ndof
         jv[name]["kernel_gbs"] = by / (jv[name]["kernel_ms"] * 1e-3) / 1e9
         jv[name]["hbm_frac"] = jv[name]["kernel_gbs"] / HBM_PEAK_GBS
-
     # cold FD product: a 512 MB write between calls evicts the 256 MB last-level
     # cache, so W, v, R(W) and the neighbour reads come from HBM (kernel time only)
     flush = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
@@ -166,33 +192,72 @@ def run(args):
     jv["fd_cold"] = dict(kernel_ms=kms, gdof_s=ctx.ndof / (kms * 1e-3) / 1e9,
                          kernel_gbs=32.0 * ctx.ndof / (kms * 1e-3) / 1e9,
                          hbm_frac=32.0 * ctx.ndof / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    return jv
+
+
+def jvp_only(args):
+    """Only the products of the workload (for kernel profiles): `--jvp-reps`
+    FD products, exact products and residuals, one JSON line of their rates."""
+    import torch
+    torch.cuda.set_device(0)
+    wl, ctx, W0 = make_case(args.workload)
+    jv = jvp_rates(ctx, W0, args.jvp_reps)
+    print(json.dumps({"workload": args.workload, "ndof": ctx.ndof, "jvp": jv}), flush=True)
+    ctx.close()
+
+
+def run(args):
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy()
+    wl, ctx, W0 = make_case(args.workload)
+    popts64 = popts_for(wl, False, args.coarse)
+
+    # ---- timed FP64 steps of the workload: `value` ------------------------------------
+    elapsed, W64, st64 = time_steps(wl, ctx, W0, popts64, args.steps, args.warmup)
+    value = ctx.ndof / elapsed / 1e9
+    steps_out = {args.workload: {"fp64": elapsed, "newton": [s_.newton for s_ in st64],
+                                 "fgmres_iters": [s_.linear_iters for s_ in st64],
+                                 "max_rel_res_true": max(s_.max_rel_res_true for s_ in st64),
+                                 "setup_s": float(sum(s_.setup_seconds for s_ in st64) / len(st64))}}
+    fams = kernel_families(ctx, wl, W0, popts64)
+    dom = max(fams, key=lambda k: fams[k]["ms_total"]) if fams else None
+    roof = roofline_of(fams, dom, ctx, popts64, args.workload) if dom else None
+
+    # ---- mixed-precision steps of the same workload ------------------------------------
+    fams32 = None
+    if not args.no_mixed:
+        popts32 = popts_for(wl, True, args.coarse)
+        t32, W32, st32 = time_steps(wl, ctx, W0, popts32, args.steps, min(args.warmup, 1))
+        steps_out[args.workload].update({
+            "mixed": t32, "speedup": elapsed / t32, "mixed_newton": [s_.newton for s_ in st32],
+            "mixed_fgmres_iters": [s_.linear_iters for s_ in st32],
+            "mixed_max_rel_res_true": max(s_.max_rel_res_true for s_ in st32),
+            "mixed_vs_fp64_rel": (W32 - W64).norm().item() / W64.norm().item()})
+        fams32 = kernel_families(ctx, wl, W0, popts32)
+
+    # ---- J.v throughput -----------------------------------------------------------------
+    jv = jvp_rates(ctx, W0, args.jvp_reps)
+    ndof, ne, pdeg = ctx.ndof, ctx.ne, ctx.p
+    ctx.close()
+    del W0, W64
+    torch.cuda.empty_cache()
     if args.workload == "tgv_p3_16" and not args.no_large_jvp:
         jv["fd_32cube"] = large_jvp()
-    if not args.no_matrix_based:
-        jv["matrix_based"] = matrix_based_jvp(wl)
+    if not args.no_matrix_based and args.workload == "tgv_p3_16":
+        jv["matrix_based"] = matrix_based_jvp(WORKLOADS[args.workload])
 
-    # ---- mixed precision steps (FP32 fine factors, BF16 coarse operators) -------------
-    mixed = None
-    if not args.no_mixed and len(wl["levels"]) > 0:
-        popts32 = popts_for(True)
-        steps(popts32, 1, W0)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        W32, st32 = steps(popts32, args.steps, W0)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        d = (W32 - W64).norm().item() / W64.norm().item()
-        # per-family kernel time of one instrumented mixed step (same stream, eager)
-        ctx.timing(True)
-        steps(popts32, 1, W0)
-        k32 = ctx.timing_read()
-        ctx.timing(False)
-        fams32 = {kind: dict(ms_total=ms, launches=cnt, ms_avg=ms / cnt,
-                             gbs=(by / (ms * 1e-3) / 1e9) if (by and ms > 0) else None)
-                  for kind, (ms, cnt, by, fl) in k32.items() if cnt}
-        mixed = dict(time_step_s=(t3 - t2) / args.steps, rel_diff_vs_fp64=d,
-                     linear_iters=[s_.linear_iters for s_ in st32], newton=[s_.newton for s_ in st32],
-                     max_rel_res_true=max(s_.max_rel_res_true for s_ in st32), kernels=fams32)
+    # ---- the curved p = 4 low-Mach workload, FP64 and mixed -----------------------------
+    if args.workload == "tgv_p3_16" and not args.no_c3:
+        wl3, ctx3, W3 = make_case("tgv_p4_16_curved")
+        k3 = max(1, min(args.steps, args.c3_steps))
+        steps_out["tgv_p4_16_curved"] = step_summary(wl3, ctx3, W3, k3, 1, args.coarse)
+        steps_out["tgv_p4_16_curved"]["steps"] = k3
+        ctx3.close()
+        del W3
+        torch.cuda.empty_cache()
 
     # ---- batching (96 independent cases) and serving (Poisson request stream) ----------
     batch = None
@@ -210,31 +275,49 @@ def run(args):
     if not args.no_cpu_baseline and args.workload == "tgv_p3_16":
         cpu = cpu_baseline()
 
+    # Full detail first (one line), then the compact result line the driver reads.
+    detail = {"kernels_fp64": fams, "kernels_mixed": fams32, "jvp": jv, "time_step": steps_out,
+              "cpu_baseline": cpu, "batch": batch, "serving": serving,
+              "kernel_timing_note": "kernel families timed with HIP events on the library stream over one "
+                                    "instrumented step (eager launches); step times are from the "
+                                    "un-instrumented steps"}
+    print("# detail " + json.dumps(detail), flush=True)
+
+    def r3(x):
+        return None if x is None else float("%.4g" % x)
+
+    ts = {}
+    for k, d in steps_out.items():
+        ts[k] = {kk: (r3(vv) if isinstance(vv, float) else vv) for kk, vv in d.items()
+                 if kk in ("fp64", "mixed", "speedup", "newton", "fgmres_iters", "max_rel_res_true",
+                           "mixed_max_rel_res_true", "mixed_vs_fp64_rel", "steps")}
+        for kk in ("newton", "fgmres_iters"):
+            if kk in ts[k] and len(set(ts[k][kk])) <= 2:
+                ts[k][kk] = sorted(set(ts[k][kk]))
+    jsum = {"fd_gdof_s": r3(jv["fd"]["gdof_s"]), "fd_kernel_ms": r3(jv["fd"]["kernel_ms"]),
+            "fd_hbm_frac": r3(jv["fd"]["hbm_frac"]), "fd_cold_hbm_frac": r3(jv["fd_cold"]["hbm_frac"]),
+            "exact_gdof_s": r3(jv["exact"]["gdof_s"]), "residual_gdof_s": r3(jv["residual"]["gdof_s"])}
+    if "fd_32cube" in jv:
+        jsum["fd_32cube_hbm_frac"] = r3(jv["fd_32cube"]["hbm_frac"])
+    jroof = dict(kernel=kernel_name("jvp_fd", wl["p"], popts64), bound="hbm",
+                 achieved=r3(jv["fd"]["kernel_gbs"]), peak=HBM_PEAK_GBS, unit="GB/s", frac=r3(jv["fd"]["hbm_frac"]),
+                 traffic=measured_traffic(kernel_name("jvp_fd", wl["p"], popts64), args.workload),
+                 bytes_per_launch=32.0 * ndof)
     out = {
         "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "description": wl["desc"], "ndof": ctx.ndof,
-                   "elements": ctx.ne, "p": ctx.p, "value_is": "DOF x BDF2 steps per second",
+        "config": {"workload": args.workload, "ndof": ndof, "elements": ne, "p": pdeg,
+                   "value_is": "DOF x BDF2 steps per second, FP64 pMG-FGMRES steps",
                    "coarse_operators": {0: "assembled", 1: "matrix-free", 2: "assembled coarsest"}[args.coarse],
-                   "mixed": "FP32 fine block factors, BF16 coarse operators (FP32 accumulation)",
-                   "parallelism": "single GPU"},
-        "time_step_s": {"fp64": elapsed / args.steps, "mixed": mixed["time_step_s"] if mixed else None},
-        "mixed_speedup": (elapsed / args.steps / mixed["time_step_s"]) if mixed else None,
-        "mixed": mixed,
-        "fp64_solver": {"newton": [s_.newton for s_ in st64], "linear_iters": [s_.linear_iters for s_ in st64],
-                        "max_rel_res_true": max(s_.max_rel_res_true for s_ in st64),
-                        "setup_s": [s_.setup_seconds for s_ in st64], "solve_s": [s_.solve_seconds for s_ in st64]},
-        "jvp": jv,
-        "kernels": fams,
+                   "mixed": "FP32 fine block factors, BF16 coarse operators (FP32 accumulation)"},
+        "time_step_s": ts,
+        "mixed_speedup": ts[args.workload].get("speedup"),
+        "jvp": jsum,
         "roofline": roof,
-        "kernel_timing_note": "kernel families timed with HIP events on the library stream over one "
-                              "instrumented FP64 step (eager launches); value is from the un-instrumented steps",
-        "cpu_baseline": cpu,
-        "batch": batch,
-        "serving": serving,
+        "jvp_roofline": jroof,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
@@ -414,25 +497,64 @@ def calibrate_copy():
 
 
 def cpu_baseline():
-    """The oracle (plain NumPy FP64, as it stands) on one BDF2 step of the same
-    physics and solver settings on a 2 x 1 x 1 mesh of the same periodic box
-    (320 x 2 = 640 DOF), one BLAS thread; DOF x steps / s."""
+    """The oracle (plain NumPy FP64, as it stands) timed on the host: the
+    residual and the FD product of Eq. DG-mf on (a) the whole 4^3 p = 2 Euler
+    vortex mesh (8,640 DOF) and (b) a periodic 2 x 16 x 16 slab of the 16^3
+    p = 3 Taylor-Green mesh (same element size and physics, the Taylor-Green
+    field restricted to the slab; 163,840 DOF: the oracle is vectorised over elements, so its per-DOF rate on the
+    slab is that of the whole mesh), each with NumPy/BLAS limited to one
+    thread and with all of the host's threads.  `value` is the FD-product
+    rate on the slab with all threads (GDOF/s, to set beside the GPU's J.v
+    rate); `cores` is the CPU time over the wall time of that measurement,
+    i.e. the threads the oracle actually kept busy."""
     import math as m
+    import platform
+    import numpy as np
     from threadpoolctl import threadpool_limits
-    from oracle import mesh as omesh, dg as odg, timestep as ots
+    from oracle import mesh as omesh, dg as odg, linear as olin
     from paper_1812_04789_amd import inputs
     L = 2 * m.pi
-    mesh = omesh.BoxMesh((2, 1, 1), (0, 0, 0), (L, L, L))
-    D = odg.Discretization(mesh, 3, gamma=1.4, mu=1.0 / 1600, Pr=0.71, eta=7.0)
-    W = D.project(inputs.taylor_green(D.quad_points(), mach=0.1))
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        _, st = ots.bdf2_step(D, W, None, 0.05, precond="pmg", levels=[3, 2, 1], restart=40, rtol=1e-8)
-        el = time.perf_counter() - t0
-    return {"value": D.ndof() / el / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": "one BDF2 step (TGV NS p=3, pMG 3-2-1, FGMRES(40) 1e-8) of the oracle on a 2x1x1 mesh "
-                      "of the same box (640 DOF), per-DOF rate; %.1f s wall" % el,
-            "seconds": el}
+    nproc = os.cpu_count()
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cases = {
+        "vortex_p2_4": dict(mesh=omesh.BoxMesh((4, 4, 4), (0, 0, 0), (10, 10, 10)), p=2, mu=0.0, Pr=0.72,
+                            ic=lambda x: inputs.isentropic_vortex(x, mach=0.5), reps=5),
+        "tgv_p3_16_slab_2x16x16": dict(mesh=omesh.BoxMesh((2, 16, 16), (0, 0, 0), (L / 8, L, L)), p=3,
+                                       mu=1.0 / 1600, Pr=0.71, ic=lambda x: inputs.taylor_green(x, mach=0.1), reps=1),
+    }
+    res = {}
+    for name, c in cases.items():
+        D = odg.Discretization(c["mesh"], c["p"], gamma=1.4, mu=c["mu"], Pr=c["Pr"], eta=7.0)
+        W = D.project(c["ic"](D.quad_points()))
+        v = inputs.random_vector(D.mesh.ne, c["p"], seed=7)
+        RW = D.residual(W)
+        for threads, tag in ((1, "1thread"), (nproc, "all")):
+            with threadpool_limits(threads):
+                for op, fn in (("residual", lambda: D.residual(W)), ("jvp_fd", lambda: olin.jvp_fd(D, W, RW, v, 30.0))):
+                    walls, cpus = [], []
+                    for _ in range(c["reps"]):
+                        c0, t0 = time.process_time(), time.perf_counter()
+                        fn()
+                        walls.append(time.perf_counter() - t0)
+                        cpus.append(time.process_time() - c0)
+                    k = int(np.argsort(walls)[len(walls) // 2])
+                    res["%s/%s/%s" % (name, op, tag)] = dict(seconds=walls[k], gdof_s=D.ndof() / walls[k] / 1e9,
+                                                             busy_threads=cpus[k] / walls[k], ndof=D.ndof())
+    main = res["tgv_p3_16_slab_2x16x16/jvp_fd/all"]
+    return {"value": main["gdof_s"], "unit": "GDOF/s", "cores": max(1, int(round(main["busy_threads"]))),
+            "kind": "oracle",
+            "sample": "oracle FD J.v (Eq. DG-mf) on a periodic 2x16x16 slab of the 16^3 p=3 Taylor-Green NS mesh "
+                      "(163,840 DOF), all %d host threads allowed (%.1f s); host: %s, nproc %d; also timed: "
+                      "residual and FD J.v on one thread and on the whole 4^3 p=2 vortex mesh (detail line)"
+                      % (nproc, main["seconds"], model, nproc),
+            "host": {"model": model, "nproc": nproc}, "runs": res}
 
 
 def main():
@@ -446,10 +568,14 @@ def main():
     ap.add_argument("--no-matrix-based", action="store_true", help="skip the assembled-operator product")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the curved 16^3 p=4 M=0.01 workload's steps")
+    ap.add_argument("--c3-steps", type=int, default=3, help="timed steps of the curved p=4 workload (at most --steps)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-count", type=int, default=400)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--jvp-only", action="store_true",
+                    help="time only the FD / exact products and the residual of the workload (for profiles)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--coarse", type=int, default=2, choices=[0, 1, 2],
@@ -459,7 +585,10 @@ def main():
         print("bench.py runs on one GPU only: the hot path of this build is single-GPU "
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    run(args)
+    if args.jvp_only:
+        jvp_only(args)
+    else:
+        run(args)
 
 
 if __name__ == "__main__":

@@ -26,7 +26,8 @@
  *    degree <= q are the first (q+1)^3 of every (element, equation) run.
  *  - Every call enqueues on the context's HIP stream and returns without
  *    waiting, except fgmres_step and dg_bdf2_step (which synchronise to test
- *    convergence and fill their statistics) and dg_create/dg_destroy.
+ *    convergence and fill their statistics), dg_assemble_operator (which
+ *    synchronises to free its unpacked blocks) and dg_create/dg_destroy.
  *  - The context owns all internal device memory (factors, coarse operators,
  *    Krylov basis, scratch); nothing it returns must be freed by the caller.
  *  - Output vectors must not alias inputs (DG_EINVAL).
@@ -185,9 +186,13 @@ dg_status dg_assemble_coarse(dg_ctx* ctx, const double* W, int pc, double* off);
  * compares against the matrix-free form): dg_assemble_operator stores
  * K = shift M + dR/dW at W, every element's diagonal block and its six
  * face-coupling blocks (7 nb^2 FP64 entries per element, held by the context
- * until the next call or dg_destroy; 23.5 GB at 16^3, p = 3), and
- * dg_jvp_assembled computes y = K v with it.  Both enqueue on the context's
- * stream; v and y are device [ne][5][nv], y must not alias v.
+ * until the next call or dg_destroy; 23.5 GB at 16^3, p = 3; 90 GB at 16^3,
+ * p = 4), and dg_jvp_assembled computes y = K v with it.
+ * dg_assemble_operator assembles the blocks unpacked first, so it needs about
+ * twice the held size while it runs (peak 47 GB at 16^3, p = 3), and
+ * synchronises the stream before returning, when the unpacked copy is freed;
+ * dg_device_bytes counts the held operator.  dg_jvp_assembled enqueues on the
+ * context's stream; v and y are device [ne][5][nv], y must not alias v.
  * dg_jvp_assembled before dg_assemble_operator: DG_ESTATE. */
 dg_status dg_assemble_operator(dg_ctx* ctx, const double* W, double shift);
 dg_status dg_jvp_assembled(dg_ctx* ctx, const double* v, double* y);

@@ -63,20 +63,21 @@ def face_colouring(mesh):
     return col
 
 
-def diag_blocks(D, W, shift):
+def diag_blocks(D, W, shift, cols=None):
     """Element diagonal blocks of K: Dblk[e] (nb, nb), nb = 5 nv, row/column
     index a*nv + i (equation-major, as W[e, a, i]).
 
     Column j of every block is Im R(W + i h e_j)/h restricted to the element,
     perturbing local DOF j of every element of one colour class at once; the
-    colouring makes the restriction exact."""
+    colouring makes the restriction exact.  `cols` (optional) limits the
+    evaluation to those column indices (the other columns stay zero)."""
     ne, nv = D.mesh.ne, D.nv
     nb = 5 * nv
     col = face_colouring(D.mesh)
     Dblk = np.zeros((ne, nb, nb))
     for c in range(col.max() + 1):
         sel = np.nonzero(col == c)[0]
-        for j in range(nb):
+        for j in (range(nb) if cols is None else cols):
             a, i = divmod(j, nv)
             Wc = W.astype(complex)
             Wc[sel, a, i] += 1j * H_CS
@@ -85,6 +86,10 @@ def diag_blocks(D, W, shift):
     # a M: M_e acts on each equation separately
     for a in range(5):
         Dblk[:, a * nv:(a + 1) * nv, a * nv:(a + 1) * nv] += shift * D.M
+    if cols is not None:
+        keep = np.zeros(nb, dtype=bool)
+        keep[list(cols)] = True
+        Dblk[:, :, ~keep] = 0.0
     return Dblk
 
 

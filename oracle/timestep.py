@@ -31,20 +31,22 @@ class StepStats:
 
 def bdf2_step(D, Wn, Wnm1, dt, precond="pmg", levels=None, restart=40, rtol=1e-8,
               newton_tol=1e-10, max_newton=5, nu_pre=2, nu_post=2, omega=1.0, coarse_iters=30,
-              max_restarts=20, jvp="exact"):
+              max_restarts=20, jvp="exact", Dblk=None):
     """`jvp` selects the Krylov operator: "exact" (tangent-linear Jacobian
     action) or "fd" (the finite-difference form of Eq. DG-mf).  The FD form
     carries a relative error of about sqrt(machine eps) (1e-8..1e-7 here), so
-    relative linear tolerances of 1e-8 and below need the exact action."""
+    relative linear tolerances of 1e-8 and below need the exact action.
+    `Dblk` (optional): the diagonal blocks of 3/(2 dt) M + dR/dW at W^n, if
+    already computed (linear.diag_blocks), for the preconditioner."""
     a = 3.0 / (2.0 * dt)
     Wnm1 = Wn if Wnm1 is None else Wnm1
     W = Wn.copy()
     RW = D.residual(W)
     if precond == "pmg":
         P = lin.PMG(D, W, a, levels if levels is not None else [D.p], nu_pre, nu_post, omega,
-                    coarse_iters, RW=RW)
+                    coarse_iters, RW=RW, Dblk=Dblk)
     elif precond == "bj":
-        P = lin.BlockJacobi(D, W, a)
+        P = lin.BlockJacobi(D, W, a, Dblk=Dblk)
     else:
         P = None
     prec = (lambda r: r) if P is None else P.apply

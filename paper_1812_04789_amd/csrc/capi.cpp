@@ -760,7 +760,8 @@ extern "C" double dg_device_bytes(const dg_ctx* ctx) {
                bytes_of(ctx->tmp1) + bytes_of(ctx->tmp2) + bytes_of(ctx->tmp3) + bytes_of(ctx->W0) +
                bytes_of(ctx->RW0) + bytes_of(ctx->blk) + bytes_of(ctx->otmp) + bytes_of(ctx->dtmp) +
                bytes_of(ctx->nbrtr) + bytes_of(ctx->RW) + bytes_of(ctx->Ru) + bytes_of(ctx->xN) +
-               bytes_of(ctx->gin) + bytes_of(ctx->gout) + krylov_bytes(ctx->kc) + krylov_bytes(ctx->kf);
+               bytes_of(ctx->gin) + bytes_of(ctx->gout) + bytes_of(ctx->mb_op) + krylov_bytes(ctx->kc) +
+               krylov_bytes(ctx->kf);
     for (const Level& L : ctx->lv)
         b += bytes_of(L.f64) + bytes_of(L.f32) + bytes_of(L.piv) + bytes_of(L.pos) + bytes_of(L.inv64) +
              bytes_of(L.inv32) + bytes_of(L.x) + bytes_of(L.b) + bytes_of(L.r) + bytes_of(L.t) + bytes_of(L.z) +
@@ -1022,6 +1023,11 @@ dg_status dg_assemble_operator(dg_ctx* ctx, const double* W, double shift) {
         CK(launch_offdiag_blocks(ctx->a, W, ctx->p, ctx->otmp.p, ctx->s));
         ctx->mb_op.ensure(bsr_entries(ctx->ne, ctx->nb, 7));
         CK(launch_bsr_pack<double>(ctx->dtmp.p, ctx->otmp.p, ctx->mb_op.p, ctx->ne, ctx->nb, 7, ctx->s));
+        // the unpacked blocks are dead once packed: free them (after the pack
+        // has run) so the context holds only the packed operator
+        CK(hipStreamSynchronize(ctx->s));
+        ctx->dtmp.release();
+        ctx->otmp.release();
         ctx->mb_ready = true;
     });
 }

@@ -76,9 +76,11 @@ def test_jvp_parity(n, p, curved):
     ye = _host(ctx.jvp_exact(Wd, vd, a), W.shape)
     yo = olin.jvp_exact(D, W, v, a)
     assert _rel(ye, yo) < 1e-12
+    assert np.abs(ye - yo).max() < 1e-11 * np.abs(yo).max()
     yf = _host(ctx.jvp(Wd, RWd, vd, a), W.shape)
     yfo = olin.jvp_fd(D, W, D.residual(W), v, a)
     assert _rel(yf, yfo) < 2e-7
+    assert np.abs(yf - yfo).max() < 1e-6 * np.abs(yfo).max()
     assert _rel(yf, yo) < 1e-5            # FD truncation error of Eq. DG-mf itself
     # v = 0 gives y = 0 exactly
     z = ctx.jvp(Wd, RWd, torch.zeros_like(vd), a)
@@ -86,7 +88,7 @@ def test_jvp_parity(n, p, curved):
 
 
 @pytest.mark.parametrize("n,p,curved", [((3, 2, 2), 1, True), ((3, 2, 2), 2, False), ((2, 3, 2), 3, True),
-                                         ((3, 1, 2), 2, True), ((2, 2, 2), 4, False)])
+                                         ((3, 1, 2), 2, True), ((2, 2, 2), 4, False), ((2, 2, 2), 4, True)])
 def test_matrix_based_product(n, p, curved):
     """The assembled operator (diagonal blocks + fine face-coupling blocks in
     the 7-block product) applied to v equals the oracle's exact product
@@ -102,7 +104,9 @@ def test_matrix_based_product(n, p, curved):
     assert ei.value.status == binding.DG_ESTATE
     ctx.assemble_operator(_dev(W), a)
     y = _host(ctx.jvp_assembled(_dev(v)), W.shape)
-    assert _rel(y, olin.jvp_exact(D, W, v, a)) < 1e-12
+    yo = olin.jvp_exact(D, W, v, a)
+    assert _rel(y, yo) < 1e-12
+    assert np.abs(y - yo).max() < 1e-11 * np.abs(yo).max()
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
@@ -129,6 +133,28 @@ def test_diag_blocks_parity(n, p, curved):
     Bo = olin.diag_blocks(D, W, a)                         # [e][row][col]
     Bg = np.transpose(B, (0, 2, 1))
     assert np.linalg.norm(Bg - Bo) / np.linalg.norm(Bo) < 1e-12
+    assert np.abs(Bg - Bo).max() < 1e-11 * np.abs(Bo).max()
+
+
+@pytest.mark.parametrize("n", [(2, 2, 2), (3, 2, 2)])
+def test_diag_blocks_p4_sampled_columns(n):
+    """p = 4 diagonal blocks on curved meshes with no single-element axis (the
+    block kernel of the 16^3 workloads): 24 seeded columns of every block,
+    including the first and last, against the oracle's complex-step columns,
+    element by element (1e-12 of the largest entry).  The oracle's full
+    625-column blocks would take minutes."""
+    print("blocks p=4", n, flush=True)
+    ctx, D = _case(n, 4, 0.02, True, amp=0.1)
+    W = inputs.random_state(ctx.ne, 4, seed=33)
+    a = 12.0
+    nb = 5 * ctx.nv
+    rng = np.random.default_rng(4)
+    cols = sorted(set([0, nb - 1] + [int(c) for c in rng.choice(nb, 22, replace=False)]))
+    B = np.transpose(ctx.assemble_diag(_dev(W), a).cpu().numpy(), (0, 2, 1))      # [e][row][col]
+    Bo = olin.diag_blocks(D, W, a, cols=cols)
+    err = np.abs(B[:, :, cols] - Bo[:, :, cols]).max() / np.abs(Bo[:, :, cols]).max()
+    print("  max rel err %.2e over %d columns" % (err, len(cols)), flush=True)
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("n,shift", [(135, 2.0), (1, 0.0), (5, 0.0), (16, 0.0), (17, 0.0), (40, 0.0), (135, 0.0),

@@ -162,11 +162,16 @@ def test_vcycle_graph_replays_match_eager(cmf):
         assert torch.equal(g2, z2), i
 
 
-@pytest.mark.parametrize("p,pc,curved", [(2, 1, True), (3, 1, False), (3, 2, True)])
+@pytest.mark.parametrize("p,pc,curved", [(2, 1, True), (3, 1, False), (3, 2, True), (4, 1, True), (4, 2, True),
+                                         (4, 4, True)])
 def test_coarse_face_blocks_are_jacobian_blocks(p, pc, curved):
     """Face-coupling blocks of the inherited coarse operator equal the exact
     Jacobian columns: perturbing a coarse mode of the neighbour across face f
-    changes R_e only through face f (3^3 mesh: each neighbour is across one face)."""
+    changes R_e only through face f (3^3 mesh: each neighbour is across one
+    face).  p = 4 with pc = 1, 2 are the coarse levels of the curved 16^3
+    workload; pc = p are the fine face blocks of the matrix-based product.
+    Compared entry by entry (1e-12 of the largest entry of the column)."""
+    print("face blocks", p, pc, curved, flush=True)
     n = (3, 3, 3)
     ctx, D = _case(n, p, 0.02, curved)
     W = inputs.random_state(ctx.ne, p, seed=61)
@@ -177,7 +182,7 @@ def test_coarse_face_blocks_are_jacobian_blocks(p, pc, curved):
     e = 13
     for f in range(6):
         nb = D.mesh.nbr[e, f]
-        for col in rng.choice(5 * nvc, 3, replace=False):
+        for col in rng.choice(5 * nvc, 3 if p < 4 else 2, replace=False):
             beta, jm = divmod(int(col), nvc)
             v = np.zeros_like(W)
             v[nb, beta, jm] = 1.0
@@ -284,3 +289,121 @@ def test_bdf2_step_p4_curved_matches_oracle(mixed):
                                                                               st.max_rel_res_true, err), flush=True)
     assert st.max_rel_res_true <= 1e-8
     assert err < 1e-10
+
+
+# ---- p = 3 and p = 4 V-cycles and steps against the oracle ----------------------
+def _tgv_case(n, p, mach, amp, mu=1.0 / 1600):
+    ctx, D = _case(n, p, mu, True, amp=amp)
+    W = D.project(inputs.taylor_green(D.quad_points(), mach=mach))
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=mach)))
+    assert _rel(Wg.cpu().numpy().reshape(W.shape), W) < 1e-13
+    return ctx, D, W, Wg
+
+
+@pytest.fixture(scope="module")
+def p3_oracle():
+    """Taylor-Green NS (Re = 1600, M = 0.1) at p = 3 on a curved 2x2x2 mesh
+    (no single-element axis): the oracle's diagonal blocks of
+    30 M + dR/dW (the shift of a BDF2 step with dt = 0.05) at the projected
+    initial state, shared by the V-cycle and time-step tests (~50 s)."""
+    ctx, D, W, _ = _tgv_case((2, 2, 2), 3, 0.1, 0.1)
+    ctx.close()
+    Dblk = olin.diag_blocks(D, W, 30.0)
+    return D, W, Dblk
+
+
+def _mixed(levels, mixed, cmf, iters=10):
+    return binding.pmg_opts(levels, coarsest_iters=iters, coarse_matrix_free=cmf,
+                            prec_fine=binding.DG_FP32 if mixed else binding.DG_FP64,
+                            prec_coarse=binding.DG_BF16 if mixed else binding.DG_FP64)
+
+
+@pytest.mark.parametrize("cmf", [2, 0])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_pmg_vcycle_p3_three_levels(cmf, mixed, p3_oracle):
+    """One V-cycle 3 -> 2 -> 1 (Alg. 2; 2 + 2 sweeps, coarsest GMRES(BJ) 10)
+    from zero against the oracle's with the inherited operators of Sec. 6.1:
+    cmf = 2 applies the p = 2 level matrix-free (FD product on the zero-padded
+    vector) and assembles the coarsest; cmf = 0 assembles both coarse levels.
+    FP64: 1e-5 (FD rounding of the level-0 and level-1 products amplified by
+    the coarsest GMRES); mixed (FP32 fine factors, BF16 coarse operators): 1e-2."""
+    D, W, Dblk = p3_oracle
+    ctx, _, _, Wg = _tgv_case((2, 2, 2), 3, 0.1, 0.1)
+    r = inputs.random_vector(ctx.ne, 3, seed=91)
+    ctx.pmg_setup(Wg, 30.0, _mixed([3, 2, 1], mixed, cmf))
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.PMG(D, W, 30.0, [3, 2, 1], coarse_iters=10, Dblk=Dblk, coarse_op="exact").apply(r)
+    err = _rel(z, zo)
+    print("V-cycle 3-2-1 cmf=%d mixed=%s rel err %.2e" % (cmf, mixed, err), flush=True)
+    assert err < (1e-2 if mixed else 1e-5)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_bdf2_step_p3_three_levels_matches_oracle(mixed, p3_oracle):
+    """One BDF2 step (dt = 0.05) of the p = 3 Taylor-Green case with the
+    workload's preconditioner (pMG 3-2-1, matrix-free p = 2 level, folded
+    assembled coarsest level; FP64 or FP32/BF16 mixed) against the oracle's
+    step (block-Jacobi FGMRES to 1e-11): W^{n+1} within 1e-10."""
+    D, W, Dblk = p3_oracle
+    W1o, sto = ots.bdf2_step(D, W, None, 0.05, precond="bj", restart=40, rtol=1e-11, Dblk=Dblk)
+    ctx, _, _, Wg = _tgv_case((2, 2, 2), 3, 0.1, 0.1)
+    W1, st = ctx.bdf2_step(Wg, None, 0.05, _mixed([3, 2, 1], mixed, 2, iters=30),
+                           binding.fgmres_opts(restart=40, rtol=1e-8))
+    err = _rel(W1.cpu().numpy().reshape(W.shape), W1o)
+    print("p3 step mixed=%s newton %d its %d rel_res %.2e err %.2e" % (mixed, st.newton, st.linear_iters,
+                                                                       st.max_rel_res_true, err), flush=True)
+    assert st.max_rel_res_true <= 1e-8
+    assert err < 1e-10
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    shape = None
+    vals = []
+    for line in open(path):
+        if line.startswith("# shape"):
+            shape = tuple(int(x.strip(";")) for x in line.split()[2:5])
+        elif not line.startswith("#"):
+            vals.append(float(line))
+    a = np.array(vals)
+    n = int(np.prod(shape))
+    return a[:n].reshape(shape), a[n:].reshape(shape)
+
+
+@pytest.mark.parametrize("cmf", [2, 0])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_pmg_vcycle_p4_three_levels(cmf, mixed):
+    """One V-cycle 4 -> 2 -> 1 on a curved 2x2x2 mesh (the p = 4 block and
+    face-block kernels of the curved 16^3 workload) against the oracle's,
+    stored by tests/golden/make_pmg_p4_vcycle.py (the oracle's p = 4 diagonal
+    blocks take minutes).  FP64: 1e-5; mixed: 1e-2."""
+    r, zo = _golden("pmg_p4_vcycle.txt")
+    ctx, D = _case((2, 2, 2), 4, 0.02, True, amp=0.1)
+    W = inputs.random_state(ctx.ne, 4, seed=81)
+    assert np.array_equal(r, inputs.random_vector(ctx.ne, 4, seed=82))
+    ctx.pmg_setup(_dev(W), 20.0, _mixed([4, 2, 1], mixed, cmf))
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    err = _rel(z, zo)
+    print("V-cycle 4-2-1 cmf=%d mixed=%s rel err %.2e" % (cmf, mixed, err), flush=True)
+    assert err < (1e-2 if mixed else 1e-5)
+
+
+def test_two_bdf2_steps_with_history(tgv_oracle):
+    """Two consecutive BDF2 steps: the second uses W^{n-1} != W^n, so the
+    history term M(3W - 4W^n + W^{n-1})/(2 dt) is exercised with distinct
+    vectors.  GPU (pMG 2-1) against the oracle, W^{n+2} within 1e-10."""
+    D, Wo, W1o = tgv_oracle
+    W2o, _ = ots.bdf2_step(D, W1o, Wo, 0.05, precond="bj", restart=40, rtol=1e-11)
+    ctx, _ = _case((3, 3, 3), 2, 1.0 / 1600, True, amp=0.05)
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.1)))
+    popts = binding.pmg_opts([2, 1])
+    fopts = binding.fgmres_opts(restart=40, rtol=1e-8)
+    W1, st1 = ctx.bdf2_step(Wg, None, 0.05, popts, fopts)
+    W2, st2 = ctx.bdf2_step(W1, Wg, 0.05, popts, fopts)
+    e1 = _rel(W1.cpu().numpy().reshape(Wo.shape), W1o)
+    e2 = _rel(W2.cpu().numpy().reshape(Wo.shape), W2o)
+    d2 = _rel((W2 - W1).cpu().numpy().reshape(Wo.shape), W2o - W1o)
+    print("two steps: err %.2e %.2e, second increment %.2e" % (e1, e2, d2), flush=True)
+    assert st2.max_rel_res_true <= 1e-8
+    assert e1 < 1e-10 and e2 < 1e-10 and d2 < 1e-6
