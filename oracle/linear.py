@@ -162,17 +162,27 @@ class PMG:
     levels: polynomial degrees, finest first (e.g. [3, 2, 1]).
     Level 0 operator: the matrix-free FD product (Eq. DG-mf); coarse operators
     are the Galerkin-inherited K_l = P_l^T K_0 P_l (Sec. 6.1), applied here as
-    P_l^T (K_0 (P_l x)) with the exact Jacobian action.  Smoother: nu damped
-    block-Jacobi sweeps; coarsest SOLVE: right-preconditioned GMRES(BJ) for a
-    fixed number of iterations.  The BJ blocks of level l are the principal
-    coarse-mode sub-blocks of the fine diagonal blocks (which is what the
-    block projection M K M^T of Sec. 6.1 gives on the diagonal)."""
+    P_l^T (K_0 (P_l x)) with the exact Jacobian action.  Coarsest SOLVE:
+    right-preconditioned GMRES(BJ) for a fixed number of iterations.  The BJ
+    blocks of level l are the principal coarse-mode sub-blocks of the fine
+    diagonal blocks (which is what the block projection M K M^T of Sec. 6.1
+    gives on the diagonal).
+
+    smoother: "bj" = nu damped block-Jacobi sweeps x <- x + omega D^-1 (b - K x);
+              "gmres" = nu iterations of right-preconditioned GMRES(BJ) on the
+              residual equation, x <- x + GMRES(K, D^-1, b - K x) (the
+              smoothers of Sec. 6 and Table MGSettings).
+    cycle:    "v" = one V-cycle from zero (Alg. 2);
+              "fmg" = the full multigrid cycle of Alg. 1 (coarsest solve, then
+              a V-cycle on each finer level from the prolonged coarser result)."""
 
     def __init__(self, D, W, shift, levels, nu_pre=2, nu_post=2, omega=1.0, coarse_iters=30,
-                 RW=None, Dblk=None, coarse_op="exact"):
+                 RW=None, Dblk=None, coarse_op="exact", smoother="bj", cycle="v"):
         """coarse_op: "exact" applies P^T K_0 P with the exact Jacobian action
         (the inherited operator of Sec. 6.1); "fd" applies P^T K_FD P with the
         finite-difference product, a matrix-free approximation of it."""
+        assert smoother in ("bj", "gmres") and cycle in ("v", "fmg")
+        self.smoother, self.cycle = smoother, cycle
         self.coarse_op = coarse_op
         self.D, self.W, self.shift = D, W, shift
         self.RW = D.residual(W) if RW is None else RW
@@ -201,6 +211,12 @@ class PMG:
         return lu_solve(LU, piv, r.reshape(ne, -1)).reshape(r.shape)
 
     def smooth(self, l, x, b, nu, x_is_zero):
+        """SMOOTH of Alg. 2 on level l from x (x = 0 when x_is_zero)."""
+        if self.smoother == "gmres":
+            if nu == 0:
+                return x
+            r = b if x_is_zero else b - self.op(l, x)
+            return x + gmres_fixed(lambda v: self.op(l, v), lambda v: self.bj(l, v), r, nu)
         for s in range(nu):
             if s == 0 and x_is_zero:
                 x = self.omega * self.bj(l, b)          # K 0 = 0
@@ -213,7 +229,7 @@ class PMG:
         return gmres_fixed(lambda x: self.op(L, x), lambda r: self.bj(L, r), b, self.coarse_iters)
 
     def vcycle(self, l, b, x=None):
-        """Alg. 2 MG_V(l, b, x)."""
+        """Alg. 2 MG_V(l, b, x); x = None is the zero initial guess."""
         if l == len(self.levels) - 1:
             return self.coarsest(b)
         zero = x is None
@@ -225,9 +241,22 @@ class PMG:
         x = x + prolong(e, nv_of(self.levels[l]))
         return self.smooth(l, x, b, self.nu_post, False)
 
+    def fmg(self, b):
+        """Alg. 1 MG_full: b_l is the restriction of the level-0 right-hand side
+        to level l; the coarsest level is solved, then every finer level runs
+        one V-cycle from the prolongation of the coarser level's result."""
+        L = len(self.levels) - 1
+        x = self.coarsest(restrict(b, self.levels[L]))
+        for l in range(L - 1, -1, -1):
+            bl = restrict(b, self.levels[l])
+            x = self.vcycle(l, bl, prolong(x, nv_of(self.levels[l])))
+        return x
+
     def apply(self, r):
         if len(self.levels) == 1:
             return self.bj(0, r)        # single grid: z = D^-1 r
+        if self.cycle == "fmg":
+            return self.fmg(r)
         return self.vcycle(0, r)
 
 
