@@ -100,7 +100,17 @@ typedef struct {
  *                 unit diagonal; one block-sparse product per iteration, and
  *                 x = D^-1 V y at the end: the same Krylov space and iterate up
  *                 to rounding); 1 = a product with K and a block-Jacobi apply
- *                 per iteration. */
+ *                 per iteration.
+ *  smoother       SMOOTH of Alg. 2 on the finer levels: 0 = nu damped
+ *                 block-Jacobi sweeps; 1 = nu iterations (at most 63) of
+ *                 right-preconditioned GMRES(BJ) on the residual equation,
+ *                 x <- x + GMRES(K_l, D_l^-1, b - K_l x) (the smoothers of
+ *                 Sec. 6, Table MGSettings: nu_pre = nu_post = 10).  omega
+ *                 is not used by the GMRES smoother.
+ *  cycle          0 = one V-cycle from zero (Alg. 2); 1 = the full multigrid
+ *                 cycle of Alg. 1 (the level-0 right-hand side restricted to
+ *                 every level, the coarsest level solved, then one V-cycle on
+ *                 each finer level from the prolonged coarser result). */
 typedef struct {
     int n_levels;
     int p_level[4];
@@ -111,6 +121,8 @@ typedef struct {
     int prec_coarse;
     int coarse_matrix_free;
     int coarsest_plain;
+    int smoother;
+    int cycle;
 } pmg_opts;
 
 /* FGMRES(restart) (Sec. 6), restart 1..63: x0 = 0, converged when the recomputed true
@@ -211,8 +223,9 @@ dg_status dg_batched_lu_solve(void* hip_stream, const double* LU, const int* piv
  * at W (Sec. 6, lagged: valid until the next pmg_setup). */
 dg_status pmg_setup(dg_ctx* ctx, const double* W, double shift, const pmg_opts* opts);
 
-/* z = one V-cycle of Alg. 2 applied to r from a zero initial guess
- * (z ~ K^-1 r).  DG_ESTATE before pmg_setup. */
+/* z = one V-cycle of Alg. 2 applied to r from a zero initial guess, or one
+ * full multigrid cycle of Alg. 1 (pmg_opts.cycle = 1) (z ~ K^-1 r).
+ * DG_ESTATE before pmg_setup. */
 dg_status pmg_apply(dg_ctx* ctx, const double* r, double* z);
 
 /* Solve K x = b by FGMRES with the current pmg preconditioner (identity if
@@ -233,6 +246,21 @@ dg_status fgmres_step(dg_ctx* ctx, const double* W, const double* RW, const doub
 dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* popts,
                        const fgmres_opts* fopts, double newton_rtol, int max_newton, double* Wnp1,
                        dg_step_stats* stats);
+
+/* One ESDIRK3 step (Sec. 4, Eq. NEWTON): the four-stage, third-order,
+ * explicit-first-stage singly diagonally implicit Runge-Kutta scheme the paper
+ * uses (Kennedy & Carpenter's tableau, as in Bijl et al. 2002; stiffly
+ * accurate, so Wnp1 is the last stage).  Stage 1 is Wn; stages 2..4 solve
+ * M (W - Wn)/(gamma dt) + sum_{j<i} (a_ij/gamma) R(W^j) + R(W) = 0 by Newton
+ * from the previous stage, linear systems (M/(gamma dt) + dR/dW) x = -R_s by
+ * fgmres_step with the pMG preconditioner set up once at Wn and lagged over
+ * all three implicit stages (the MFL option of Sec. 7.3).  Per stage Newton
+ * stops as in dg_bdf2_step (1e-14 floor with a = 1/(gamma dt)); stats sum the
+ * Newton and FGMRES iterations of the stages, res0 is the second stage's
+ * initial residual and res_final the last stage's final one; DG_ENOCONV if a
+ * stage did not converge.  Holds 4 more N-vectors than dg_bdf2_step. */
+dg_status dg_esdirk3_step(dg_ctx* ctx, const double* Wn, double dt, const pmg_opts* popts, const fgmres_opts* fopts,
+                          double newton_rtol, int max_newton, double* Wnp1, dg_step_stats* stats);
 
 /* pmg_apply replays the V-cycle as a HIP graph captured after each
  * pmg_setup (enabled by default; the launch sequence of a V-cycle is fixed

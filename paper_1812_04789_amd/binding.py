@@ -33,7 +33,7 @@ class PmgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("p_level", ctypes.c_int * 4), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("coarsest_iters", ctypes.c_int),
                 ("prec_fine", ctypes.c_int), ("prec_coarse", ctypes.c_int), ("coarse_matrix_free", ctypes.c_int),
-                ("coarsest_plain", ctypes.c_int)]
+                ("coarsest_plain", ctypes.c_int), ("smoother", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
 class FgmresOpts(ctypes.Structure):
@@ -115,6 +115,8 @@ SIGNATURES = {
     "dg_timing_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "dg_bdf2_step": (_I, [_P, _P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
                           ctypes.POINTER(StepStats)]),
+    "dg_esdirk3_step": (_I, [_P, _P, _D, ctypes.POINTER(PmgOpts), ctypes.POINTER(FgmresOpts), _D, _I, _P,
+                             ctypes.POINTER(StepStats)]),
     "dg_batch_create": (_I, [ctypes.POINTER(CaseDesc), _I, _P, ctypes.POINTER(_P)]),
     "dg_batch_destroy": (_I, [_P]),
     "dg_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -182,16 +184,28 @@ class DGError(RuntimeError):
         self.status = status
 
 
+SMOOTH_BJ, SMOOTH_GMRES = 0, 1
+CYCLE_V, CYCLE_FMG = 0, 1
+
+
 def pmg_opts(levels, nu_pre=2, nu_post=2, omega=1.0, coarsest_iters=30, prec_fine=DG_FP64,
-             prec_coarse=DG_FP64, coarse_matrix_free=1, coarsest_plain=0):
+             prec_coarse=DG_FP64, coarse_matrix_free=1, coarsest_plain=0, smoother=SMOOTH_BJ, cycle=CYCLE_V):
     o = PmgOpts()
     o.n_levels = len(levels)
     for i, p in enumerate(levels):
         o.p_level[i] = int(p)
     o.nu_pre, o.nu_post, o.omega, o.coarsest_iters = nu_pre, nu_post, omega, coarsest_iters
     o.prec_fine, o.prec_coarse, o.coarse_matrix_free = prec_fine, prec_coarse, coarse_matrix_free
-    o.coarsest_plain = coarsest_plain
+    o.coarsest_plain, o.smoother, o.cycle = coarsest_plain, smoother, cycle
     return o
+
+
+def paper_pmg_opts(levels, prec_fine=DG_FP64, prec_coarse=DG_FP64, coarse_matrix_free=2):
+    """The paper's preconditioner (Sec. 6, Alg. 1, Table MGSettings): full
+    multigrid, GMRES(BJ) smoothers with 10 iterations on the finer levels, a
+    30-iteration coarsest GMRES (block Jacobi in place of the paper's BILU)."""
+    return pmg_opts(levels, nu_pre=10, nu_post=10, coarsest_iters=30, prec_fine=prec_fine, prec_coarse=prec_coarse,
+                    coarse_matrix_free=coarse_matrix_free, smoother=SMOOTH_GMRES, cycle=CYCLE_FMG)
 
 
 def fgmres_opts(restart=30, rtol=1e-8, max_restarts=20, jvp_exact=1):
@@ -376,6 +390,14 @@ class Context:
         fl = (ctypes.c_double * k)()
         self._check(self.lib.dg_timing_read(self.h, ms, cnt, by, fl))
         return {KERNEL_KINDS[i]: (ms[i], cnt[i], by[i], fl[i]) for i in range(k)}
+
+    def esdirk3_step(self, Wn, dt, popts, fopts, newton_rtol=1e-10, max_newton=5, Wnp1=None):
+        Wnp1 = self.empty() if Wnp1 is None else Wnp1
+        st = StepStats()
+        self._check(self.lib.dg_esdirk3_step(self.h, self._vec(Wn, "Wn"), float(dt), ctypes.byref(popts),
+                                             ctypes.byref(fopts), float(newton_rtol), int(max_newton),
+                                             self._vec(Wnp1, "Wnp1"), ctypes.byref(st)))
+        return Wnp1, st
 
     def bdf2_step(self, Wn, Wnm1, dt, popts, fopts, newton_rtol=1e-10, max_newton=5, Wnp1=None):
         Wnp1 = self.empty() if Wnp1 is None else Wnp1

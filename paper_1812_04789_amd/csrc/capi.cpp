@@ -92,6 +92,7 @@ struct Level {
     DBuf<double> inv64;
     DBuf<float> inv32;
     DBuf<double> x, b, r, t, z;
+    DBuf<double> fb, fx;       // full multigrid: this level's restricted right-hand side and iterate
     // assembled inherited operator: diagonal + 6 face blocks per element
     bool assembled = false;
     int op_prec = DG_FP64;
@@ -99,7 +100,8 @@ struct Level {
     DBuf<float> op32;
     DBuf<unsigned short> op16;
     void release() { inv64.release(); inv32.release(); op64.release(); op32.release(); op16.release();
-                     f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release(); }
+                     f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release();
+                     fb.release(); fx.release(); }
 };
 
 std::mutex g_tab_mu;
@@ -130,9 +132,11 @@ struct dg_ctx {
     DBuf<double> W0, RW0, blk, otmp, dtmp, nbrtr;
     std::vector<Level> lv;
     Krylov kc;                              // coarsest-level GMRES
+    std::vector<Krylov> ks;                 // GMRES(BJ) smoothers of the finer levels
     Krylov kf;                              // outer FGMRES
     // Newton
     DBuf<double> RW, Ru, xN;
+    DBuf<double> Rst, Est;                  // ESDIRK3: R of the completed stages (3 N), their weighted sum (N)
     // V-cycle replayed as a HIP graph (captured on a private stream after setup)
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
@@ -257,8 +261,29 @@ void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
     CK(launch_restrict(ctx->ne, ctx->nv, L.nv, ctx->tmp2.p, y, ctx->s));
 }
 
+void gmres_fixed_dev(dg_ctx* ctx, int l, Krylov& K, const double* b, double* x, int iters);
+
+// SMOOTH of Alg. 2 on level l: nu damped block-Jacobi sweeps, or (smoother =
+// 1) nu iterations of right-preconditioned GMRES(BJ) on the residual
+// equation, x <- x + GMRES(K_l, D_l^-1, b - K_l x).
 void smooth(dg_ctx* ctx, int l, double* x, const double* b, int nu, bool x_zero) {
     Level& L = ctx->lv[l];
+    if (ctx->popt.smoother == 1) {
+        if (nu == 0) {
+            if (x_zero) CK(launch_fill(L.ndof, 0.0, x, ctx->s));
+            return;
+        }
+        const double* r = b;
+        if (!x_zero) {
+            level_op(ctx, l, x, L.t.p);
+            CK(launch_axpby(L.ndof, 1.0, b, -1.0, L.t.p, L.r.p, ctx->s));
+            r = L.r.p;
+        }
+        gmres_fixed_dev(ctx, l, ctx->ks[l], r, L.z.p, nu);
+        if (x_zero) CK(launch_copy(L.ndof, L.z.p, x, ctx->s));
+        else CK(launch_axpby(L.ndof, 1.0, L.z.p, 1.0, x, x, ctx->s));
+        return;
+    }
     const double om = ctx->popt.omega;
     for (int s = 0; s < nu; ++s) {
         if (s == 0 && x_zero) {
@@ -339,6 +364,13 @@ void coarse_gmres(dg_ctx* ctx, int l, const double* b, double* x, int iters) {
         bj_apply(ctx, l, L.t.p, x);
         return;
     }
+    gmres_fixed_dev(ctx, l, K, b, x, iters);
+}
+
+// Right-preconditioned GMRES(BJ) on level l from x = 0 for exactly `iters`
+// Arnoldi steps (K sized for this level and at least `iters`), all on the device.
+void gmres_fixed_dev(dg_ctx* ctx, int l, Krylov& K, const double* b, double* x, int iters) {
+    const size_t n = ctx->lv[l].ndof;
     dot(ctx, b, b, n, K.sc.p + 3);
     CK(launch_init_g(K.g.p, iters + 1, K.sc.p + 3, ctx->s));
     CK(launch_scale_dev(n, b, K.g.p, 1, K.V.p, ctx->s));
@@ -353,8 +385,8 @@ void coarse_gmres(dg_ctx* ctx, int l, const double* b, double* x, int iters) {
     CK(launch_multi_axpy(n, iters, K.y.p, 1, K.Z.p, n, x, ctx->s));
 }
 
-// Alg. 2: MG_V(l, b_l, x_l = 0)
-void vcycle(dg_ctx* ctx, int l, const double* b, double* x) {
+// Alg. 2: MG_V(l, b_l, x_l), from x_l = 0 (x_zero) or from the given x_l.
+void vcycle(dg_ctx* ctx, int l, const double* b, double* x, bool x_zero = true) {
     const int Lc = (int)ctx->lv.size() - 1;
     if (l == Lc) {
         coarse_gmres(ctx, l, b, x, ctx->popt.coarsest_iters);
@@ -362,13 +394,37 @@ void vcycle(dg_ctx* ctx, int l, const double* b, double* x) {
     }
     Level& L = ctx->lv[l];
     Level& C = ctx->lv[l + 1];
-    smooth(ctx, l, x, b, ctx->popt.nu_pre, true);
+    smooth(ctx, l, x, b, ctx->popt.nu_pre, x_zero);
     level_op(ctx, l, x, L.t.p);
     CK(launch_axpby(L.ndof, 1.0, b, -1.0, L.t.p, L.r.p, ctx->s));
     CK(launch_restrict(ctx->ne, L.nv, C.nv, L.r.p, C.b.p, ctx->s));
     vcycle(ctx, l + 1, C.b.p, C.x.p);
     CK(launch_prolong_add(ctx->ne, L.nv, C.nv, C.x.p, x, 0, ctx->s));
     smooth(ctx, l, x, b, ctx->popt.nu_post, false);
+}
+
+// Alg. 1: MG_full.  b_l is the level-0 right-hand side restricted to level l;
+// the coarsest level is solved from zero, then each finer level runs one
+// V-cycle from the prolongation of the coarser level's result.
+void fmg(dg_ctx* ctx, const double* b, double* z) {
+    const int Lc = (int)ctx->lv.size() - 1;
+    const int nv0 = ctx->lv[0].nv;
+    Level& C = ctx->lv[Lc];
+    CK(launch_restrict(ctx->ne, nv0, C.nv, b, C.fb.p, ctx->s));
+    coarse_gmres(ctx, Lc, C.fb.p, C.fx.p, ctx->popt.coarsest_iters);
+    for (int l = Lc - 1; l >= 0; --l) {
+        Level& L = ctx->lv[l];
+        Level& U = ctx->lv[l + 1];
+        const double* bl = b;
+        double* xl = z;
+        if (l > 0) {
+            CK(launch_restrict(ctx->ne, nv0, L.nv, b, L.fb.p, ctx->s));
+            bl = L.fb.p;
+            xl = L.fx.p;
+        }
+        CK(launch_prolong_add(ctx->ne, L.nv, U.nv, U.fx.p, xl, 1, ctx->s));
+        vcycle(ctx, l, bl, xl, false);
+    }
 }
 
 void drop_graph(dg_ctx* ctx) {
@@ -378,6 +434,7 @@ void drop_graph(dg_ctx* ctx) {
 
 void pmg_apply_eager(dg_ctx* ctx, const double* r, double* z) {
     if (ctx->lv.size() == 1) bj_apply(ctx, 0, r, z);
+    else if (ctx->popt.cycle == 1) fmg(ctx, r, z);
     else vcycle(ctx, 0, r, z);
 }
 
@@ -435,6 +492,10 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
         fail(ctx, DG_EINVAL, "prec_coarse must be FP64, FP32 or BF16");
     if (o->coarse_matrix_free < 0 || o->coarse_matrix_free > 2) fail(ctx, DG_EINVAL, "coarse_matrix_free must be 0, 1 or 2");
     if (o->coarsest_plain != 0 && o->coarsest_plain != 1) fail(ctx, DG_EINVAL, "coarsest_plain must be 0 or 1");
+    if (o->smoother != 0 && o->smoother != 1) fail(ctx, DG_EINVAL, "smoother must be 0 (BJ sweeps) or 1 (GMRES(BJ))");
+    if (o->cycle != 0 && o->cycle != 1) fail(ctx, DG_EINVAL, "cycle must be 0 (V-cycle) or 1 (full multigrid)");
+    if (o->smoother == 1 && (o->nu_pre > 63 || o->nu_post > 63))
+        fail(ctx, DG_EINVAL, "GMRES smoother iterations must be at most 63");
 }
 
 double lu_bytes(dg_ctx* ctx, int nb, double s) { return ctx->ne * 2.0 * s * (double)nb * nb; }
@@ -569,6 +630,25 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         const Level& Lc = ctx->lv.back();
         ctx->kc.ensure(o->coarsest_iters, Lc.ndof);
     }
+    // GMRES(BJ) smoothers: one Krylov workspace per finer level
+    if (o->n_levels > 1 && o->smoother == 1) {
+        if (ctx->ks.size() < (size_t)(o->n_levels - 1)) ctx->ks.resize(o->n_levels - 1);
+        const int m = std::max(1, std::max(o->nu_pre, o->nu_post));
+        for (int l = 0; l < o->n_levels - 1; ++l) ctx->ks[l].ensure(m, ctx->lv[l].ndof);
+    }
+    for (size_t l = (o->smoother == 1 ? (size_t)std::max(0, o->n_levels - 1) : 0); l < ctx->ks.size(); ++l)
+        ctx->ks[l].release();
+    // full multigrid: restricted right-hand sides and iterates of the coarse levels
+    for (int l = 1; l < o->n_levels; ++l) {
+        Level& L = ctx->lv[l];
+        if (o->cycle == 1) {
+            L.fb.ensure(L.ndof);
+            L.fx.ensure(L.ndof);
+        } else {
+            L.fb.release();
+            L.fx.release();
+        }
+    }
     ctx->pmg_ready = true;
 }
 
@@ -648,6 +728,51 @@ void ensure_scratch(dg_ctx* ctx) {
     ctx->tmp3.ensure(ctx->N);
 }
 
+// Newton iterations on one nonlinear system of a time step (Sec. 4, Eq.
+// NEWTON): unsteady() evaluates R(W) into ctx->RW and the system's residual
+// R_u(W) into ctx->Ru and returns ||R_u||; each iteration solves
+// K x = -R_u by FGMRES (K linearised at the current W, shift of the lagged
+// preconditioner) and sets W += x.  Stops when ||R_u|| <= rtol ||R_u(W_0)||
+// or below `floor`.  Accumulates into loc; returns whether it converged.
+template <class U>
+bool newton_solve(dg_ctx* ctx, double* W, U&& unsteady, const fgmres_opts* fo, double rtol, int max_newton,
+                  double floor, dg_step_stats& loc, double& worst, double& r0_out, double& r_out) {
+    const size_t n = ctx->N;
+    double r = unsteady();
+    if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
+    const double r0 = r;
+    bool conv = false;
+    for (int k = 0; k < max_newton; ++k) {
+        if (r <= rtol * r0 || r <= floor) {
+            conv = true;
+            break;
+        }
+        CK(launch_axpby(n, -1.0, ctx->Ru.p, 0.0, nullptr, ctx->tmp3.p, ctx->s));   // b = -R_u
+        // fgmres uses tmp2/tmp3 internally: keep b in Ru (negated in place)
+        CK(launch_copy(n, ctx->tmp3.p, ctx->Ru.p, ctx->s));
+        fgmres_stats fs{};
+        fgmres_impl(ctx, W, ctx->RW.p, ctx->Ru.p, ctx->xN.p, fo, &fs);
+        loc.linear_iters += fs.iters;
+        if (fs.rel_res_true > worst) worst = fs.rel_res_true;
+        CK(launch_axpby(n, 1.0, ctx->xN.p, 1.0, W, W, ctx->s));
+        loc.newton++;
+        r = unsteady();
+        if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
+    }
+    if (!conv && (r <= rtol * r0 || r <= floor)) conv = true;
+    r0_out = r0;
+    r_out = r;
+    return conv;
+}
+
+// 1e-14 a ||M Wn||: the rounding floor of a step's Newton residual (the size
+// of the unsteady term a M W at rounding precision).
+double newton_floor(dg_ctx* ctx, const double* Wn, double a) {
+    CK(launch_mass(ctx->a, Wn, ctx->tmp1.p, 1.0, 0, ctx->s));
+    dot(ctx, ctx->tmp1.p, ctx->tmp1.p, ctx->N, sc(ctx, S_N_M2));
+    return 1e-14 * a * std::sqrt(read_scalar(ctx, sc(ctx, S_N_M2)));
+}
+
 void bdf2_impl(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, const pmg_opts* po,
                const fgmres_opts* fo, double rtol, int max_newton, double* Wnp1, dg_step_stats* st) {
     if (!(dt > 0.0) || !(rtol > 0.0) || max_newton < 1) fail(ctx, DG_EINVAL, "bad dt / newton_rtol / max_newton");
@@ -665,10 +790,7 @@ void bdf2_impl(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, con
     pmg_setup_impl(ctx, Wn, a, po);
     CK(hipStreamSynchronize(ctx->s));
     auto t1 = std::chrono::steady_clock::now();
-    // ||M Wn|| for the rounding floor
-    CK(launch_mass(ctx->a, Wn, ctx->tmp1.p, 1.0, 0, ctx->s));
-    dot(ctx, ctx->tmp1.p, ctx->tmp1.p, n, sc(ctx, S_N_M2));
-    const double floor = 1e-14 * a * std::sqrt(read_scalar(ctx, sc(ctx, S_N_M2)));
+    const double floor = newton_floor(ctx, Wn, a);
     auto unsteady = [&]() -> double {
         timed(ctx, DG_K_RESIDUAL, 16.0 * (double)ctx->N, 0.0, [&] { return launch_residual(ctx->a, W, ctx->RW.p, ctx->s); });
         // t = 3 W - 4 Wn + Wnm1 ; Ru = M t / (2 dt) + RW
@@ -679,37 +801,84 @@ void bdf2_impl(dg_ctx* ctx, const double* Wn, const double* Wnm1, double dt, con
         dot(ctx, ctx->Ru.p, ctx->Ru.p, n, sc(ctx, S_N_R2));
         return std::sqrt(read_scalar(ctx, sc(ctx, S_N_R2)));
     };
-    double r = unsteady();
-    if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
-    loc.res0 = r;
-    double worst = 0.0;
-    bool conv = false;
-    for (int k = 0; k < max_newton; ++k) {
-        if (r <= rtol * loc.res0 || r <= floor) {
-            conv = true;
-            break;
-        }
-        CK(launch_axpby(n, -1.0, ctx->Ru.p, 0.0, nullptr, ctx->tmp3.p, ctx->s));   // b = -R_u
-        // fgmres uses tmp2/tmp3 internally: keep b in Ru (negated in place)
-        CK(launch_copy(n, ctx->tmp3.p, ctx->Ru.p, ctx->s));
-        fgmres_stats fs{};
-        fgmres_impl(ctx, W, ctx->RW.p, ctx->Ru.p, ctx->xN.p, fo, &fs);
-        loc.linear_iters += fs.iters;
-        if (fs.rel_res_true > worst) worst = fs.rel_res_true;
-        CK(launch_axpby(n, 1.0, ctx->xN.p, 1.0, W, W, ctx->s));
-        loc.newton++;
-        r = unsteady();
-        if (!std::isfinite(r)) fail(ctx, DG_ENONFINITE, "non-finite unsteady residual");
-    }
-    if (!conv && (r <= rtol * loc.res0 || r <= floor)) conv = true;
+    double worst = 0.0, r0 = 0.0, r = 0.0;
+    const bool conv = newton_solve(ctx, W, unsteady, fo, rtol, max_newton, floor, loc, worst, r0, r);
     CK(hipStreamSynchronize(ctx->s));
     auto t2 = std::chrono::steady_clock::now();
+    loc.res0 = r0;
     loc.res_final = r;
     loc.max_rel_res_true = worst;
     loc.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
     loc.solve_seconds = std::chrono::duration<double>(t2 - t1).count();
     if (st) *st = loc;
     if (!conv) fail(ctx, DG_ENOCONV, "Newton did not converge");
+}
+
+// ESDIRK3 (Sec. 4): the four-stage, third-order, explicit-first-stage,
+// singly diagonally implicit Runge-Kutta scheme of Kennedy & Carpenter used
+// by Bijl et al. (2002), published rational tableau; stiffly accurate.
+constexpr double ESD_G = 1767732205903.0 / 4055673282236.0;
+constexpr double ESD_A[4][4] = {
+    {0.0, 0.0, 0.0, 0.0},
+    {ESD_G, ESD_G, 0.0, 0.0},
+    {2746238789719.0 / 10658868560708.0, -640167445237.0 / 6845629431997.0, ESD_G, 0.0},
+    {1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0, 11266239266428.0 / 11593286722821.0,
+     ESD_G}};
+
+// One ESDIRK3 step: W^1 = Wn; stages i = 2..4 solve
+//   M (W - Wn) / (gamma dt) + sum_{j<i} (a_ij / gamma) R(W^j) + R(W) = 0
+// by Newton from the previous stage (iteration matrix M/(gamma dt) + dR/dW,
+// one pMG setup at Wn lagged over all stages); Wnp1 = W^4.
+void esdirk3_impl(dg_ctx* ctx, const double* Wn, double dt, const pmg_opts* po, const fgmres_opts* fo, double rtol,
+                  int max_newton, double* Wnp1, dg_step_stats* st) {
+    if (!(dt > 0.0) || !(rtol > 0.0) || max_newton < 1) fail(ctx, DG_EINVAL, "bad dt / newton_rtol / max_newton");
+    const size_t n = ctx->N;
+    const double a = 1.0 / (ESD_G * dt);
+    dg_step_stats loc{};
+    ctx->RW.ensure(n);
+    ctx->Ru.ensure(n);
+    ctx->xN.ensure(n);
+    ctx->Rst.ensure(3 * n);
+    ctx->Est.ensure(n);
+    double* W = Wnp1;
+    CK(launch_copy(n, Wn, W, ctx->s));
+    CK(hipStreamSynchronize(ctx->s));
+    auto t0 = std::chrono::steady_clock::now();
+    pmg_setup_impl(ctx, Wn, a, po);
+    CK(hipStreamSynchronize(ctx->s));
+    auto t1 = std::chrono::steady_clock::now();
+    const double floor = newton_floor(ctx, Wn, a);
+    CK(launch_copy(n, ctx->RW0.p, ctx->Rst.p, ctx->s));                 // R(W^1) = R(Wn), from the setup
+    double worst = 0.0, r0 = 0.0, r = 0.0;
+    bool conv = true;
+    for (int i = 1; i < 4; ++i) {
+        // E = sum_{j<i} (a_ij / gamma) R(W^j)
+        CK(launch_axpby(n, ESD_A[i][0] / ESD_G, ctx->Rst.p, 0.0, nullptr, ctx->Est.p, ctx->s));
+        for (int j = 1; j < i; ++j)
+            CK(launch_axpby(n, ESD_A[i][j] / ESD_G, ctx->Rst.p + (size_t)j * n, 1.0, ctx->Est.p, ctx->Est.p, ctx->s));
+        auto unsteady = [&]() -> double {
+            timed(ctx, DG_K_RESIDUAL, 16.0 * (double)ctx->N, 0.0, [&] { return launch_residual(ctx->a, W, ctx->RW.p, ctx->s); });
+            // Ru = a M (W - Wn) + E + RW
+            CK(launch_axpby(n, 1.0, W, -1.0, Wn, ctx->tmp1.p, ctx->s));
+            CK(launch_axpby(n, 1.0, ctx->RW.p, 1.0, ctx->Est.p, ctx->Ru.p, ctx->s));
+            CK(launch_mass(ctx->a, ctx->tmp1.p, ctx->Ru.p, a, 1, ctx->s));
+            dot(ctx, ctx->Ru.p, ctx->Ru.p, n, sc(ctx, S_N_R2));
+            return std::sqrt(read_scalar(ctx, sc(ctx, S_N_R2)));
+        };
+        double rs0 = 0.0;
+        conv = newton_solve(ctx, W, unsteady, fo, rtol, max_newton, floor, loc, worst, rs0, r) && conv;
+        if (i == 1) r0 = rs0;
+        if (i < 3) CK(launch_copy(n, ctx->RW.p, ctx->Rst.p + (size_t)i * n, ctx->s));
+    }
+    CK(hipStreamSynchronize(ctx->s));
+    auto t2 = std::chrono::steady_clock::now();
+    loc.res0 = r0;
+    loc.res_final = r;
+    loc.max_rel_res_true = worst;
+    loc.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
+    loc.solve_seconds = std::chrono::duration<double>(t2 - t1).count();
+    if (st) *st = loc;
+    if (!conv) fail(ctx, DG_ENOCONV, "Newton did not converge in some stage");
 }
 
 template <class F>
@@ -761,11 +930,12 @@ extern "C" double dg_device_bytes(const dg_ctx* ctx) {
                bytes_of(ctx->RW0) + bytes_of(ctx->blk) + bytes_of(ctx->otmp) + bytes_of(ctx->dtmp) +
                bytes_of(ctx->nbrtr) + bytes_of(ctx->RW) + bytes_of(ctx->Ru) + bytes_of(ctx->xN) +
                bytes_of(ctx->gin) + bytes_of(ctx->gout) + bytes_of(ctx->mb_op) + krylov_bytes(ctx->kc) +
-               krylov_bytes(ctx->kf);
+               krylov_bytes(ctx->kf) + bytes_of(ctx->Rst) + bytes_of(ctx->Est);
+    for (const Krylov& K : ctx->ks) b += krylov_bytes(K);
     for (const Level& L : ctx->lv)
         b += bytes_of(L.f64) + bytes_of(L.f32) + bytes_of(L.piv) + bytes_of(L.pos) + bytes_of(L.inv64) +
              bytes_of(L.inv32) + bytes_of(L.x) + bytes_of(L.b) + bytes_of(L.r) + bytes_of(L.t) + bytes_of(L.z) +
-             bytes_of(L.op64) + bytes_of(L.op32) + bytes_of(L.op16);
+             bytes_of(L.op64) + bytes_of(L.op32) + bytes_of(L.op16) + bytes_of(L.fb) + bytes_of(L.fx);
     return b;
 }
 
@@ -790,6 +960,9 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         const bool fold = assembled && l == po->n_levels - 1 && nbl <= INV_POLICY_N && nbl <= FOLD_MAX_N &&
                           po->coarsest_plain == 0;
         b += 2 * ndl * 4 + 5 * ndl * 8;                                           // pivots, positions, vectors
+        if (po->cycle == 1 && l > 0) b += 2 * ndl * 8;                           // full multigrid b_l, x_l
+        if (po->smoother == 1 && l < po->n_levels - 1)                            // GMRES(BJ) smoother
+            b += krylov(std::max(1, std::max(po->nu_pre, po->nu_post)), ndl);
         if (assembled) {
             tmp = std::max(tmp, 7 * sz * 8);
             b += (double)bsr_entries((int)ne, (int)nbl, fold ? 6 : 7) *
@@ -924,7 +1097,8 @@ dg_status dg_destroy(dg_ctx* ctx) {
     ctx->mb_op.release();
     for (auto& L : ctx->lv) L.release();
     ctx->kc.release(); ctx->kf.release();
-    ctx->RW.release(); ctx->Ru.release(); ctx->xN.release();
+    ctx->RW.release(); ctx->Ru.release(); ctx->xN.release(); ctx->Rst.release(); ctx->Est.release();
+    for (auto& K : ctx->ks) K.release();
     delete ctx;
     return DG_OK;
 }
@@ -1093,6 +1267,16 @@ dg_status dg_bdf2_step(dg_ctx* ctx, const double* Wn, const double* Wnm1, double
         no_alias(ctx, Wnp1, Wn, "Wnp1/Wn");
         no_alias(ctx, Wnp1, Wnm1, "Wnp1/Wnm1");
         bdf2_impl(ctx, Wn, Wnm1, dt, popts, fopts, newton_rtol, max_newton, Wnp1, stats);
+    });
+}
+
+dg_status dg_esdirk3_step(dg_ctx* ctx, const double* Wn, double dt, const pmg_opts* popts, const fgmres_opts* fopts,
+                          double newton_rtol, int max_newton, double* Wnp1, dg_step_stats* stats) {
+    return guarded(ctx, [&] {
+        need(ctx, Wn, "Wn");
+        need(ctx, Wnp1, "Wnp1");
+        no_alias(ctx, Wnp1, Wn, "Wnp1/Wn");
+        esdirk3_impl(ctx, Wn, dt, popts, fopts, newton_rtol, max_newton, Wnp1, stats);
     });
 }
 

@@ -407,3 +407,107 @@ def test_two_bdf2_steps_with_history(tgv_oracle):
     print("two steps: err %.2e %.2e, second increment %.2e" % (e1, e2, d2), flush=True)
     assert st2.max_rel_res_true <= 1e-8
     assert e1 < 1e-10 and e2 < 1e-10 and d2 < 1e-6
+
+
+# ---- the paper's solver configuration: full multigrid, GMRES(BJ) smoothers, ESDIRK3 ----
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fmg_gmres_smoothers_p3_matches_oracle(mixed, p3_oracle):
+    """One full multigrid cycle (Alg. 1) 3 -> 2 -> 1 with GMRES(BJ) smoothers
+    (4 iterations per smoothing here) and a 10-step coarsest GMRES(BJ), against
+    the oracle's (inherited operators of Sec. 6.1).  FP64: 1e-5 (FD rounding
+    through the nonlinear GMRES smoothers); mixed: 1e-2."""
+    D, W, Dblk = p3_oracle
+    ctx, _, _, Wg = _tgv_case((2, 2, 2), 3, 0.1, 0.1)
+    r = inputs.random_vector(ctx.ne, 3, seed=93)
+    opts = binding.pmg_opts([3, 2, 1], nu_pre=4, nu_post=4, coarsest_iters=10, coarse_matrix_free=2,
+                            prec_fine=binding.DG_FP32 if mixed else binding.DG_FP64,
+                            prec_coarse=binding.DG_BF16 if mixed else binding.DG_FP64,
+                            smoother=binding.SMOOTH_GMRES, cycle=binding.CYCLE_FMG)
+    ctx.pmg_setup(Wg, 30.0, opts)
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.PMG(D, W, 30.0, [3, 2, 1], nu_pre=4, nu_post=4, coarse_iters=10, Dblk=Dblk, coarse_op="exact",
+                  smoother="gmres", cycle="fmg").apply(r)
+    err = _rel(z, zo)
+    print("FMG/GMRES 3-2-1 mixed=%s rel err %.2e" % (mixed, err), flush=True)
+    assert err < (1e-2 if mixed else 1e-5)
+
+
+@pytest.mark.parametrize("smoother,cycle", [(0, 1), (1, 0)])
+def test_fmg_and_gmres_smoother_separately(smoother, cycle):
+    """FMG with block-Jacobi sweeps, and the V-cycle with GMRES(BJ) smoothers,
+    on a curved p = 2 case with two levels, against the oracle (1e-5)."""
+    ctx, D = _case((2, 2, 2), 2, 0.02, True)
+    W = inputs.random_state(ctx.ne, 2, seed=95)
+    r = inputs.random_vector(ctx.ne, 2, seed=96)
+    a = 20.0
+    opts = binding.pmg_opts([2, 1], nu_pre=3, nu_post=2, coarsest_iters=8, coarse_matrix_free=0,
+                            smoother=smoother, cycle=cycle)
+    ctx.pmg_setup(_dev(W), a, opts)
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.PMG(D, W, a, [2, 1], nu_pre=3, nu_post=2, coarse_iters=8, coarse_op="exact",
+                  smoother=("gmres" if smoother else "bj"), cycle=("fmg" if cycle else "v")).apply(r)
+    err = _rel(z, zo)
+    print("smoother=%d cycle=%d rel err %.2e" % (smoother, cycle, err), flush=True)
+    assert err < 1e-5
+
+
+def test_fmg_graph_replays_match_eager():
+    """The full multigrid cycle with GMRES smoothers replays as a captured HIP
+    graph: every replay equals the eager cycle bitwise."""
+    ctx, _ = _case((2, 3, 2), 2, 0.02, True)
+    W = _dev(inputs.random_state(ctx.ne, 2, seed=97))
+    r1 = _dev(inputs.random_vector(ctx.ne, 2, seed=98))
+    ctx.pmg_setup(W, 20.0, binding.paper_pmg_opts([2, 1]))
+    ctx.use_graphs(False)
+    z1 = ctx.pmg_apply(r1).clone()
+    ctx.use_graphs(True)
+    for i in range(3):
+        g1 = ctx.pmg_apply(r1)
+        ctx.residual(W)
+        torch.cuda.synchronize()
+        assert torch.equal(g1, z1), i
+
+
+def test_esdirk3_step_matches_oracle(tgv_oracle):
+    """One ESDIRK3 step (Sec. 4) of the Taylor-Green NS case (p = 2, curved
+    3^3) with the paper's preconditioner (full multigrid 2 -> 1, GMRES(BJ)
+    10/10 smoothers, coarsest GMRES(BJ) 30, lagged over the three implicit
+    stages) against the oracle's ESDIRK3 step (block-Jacobi FGMRES to 1e-11):
+    W^{n+1} within 1e-10."""
+    D, Wo, _ = tgv_oracle
+    W1o, sto = ots.esdirk3_step(D, Wo, 0.05, precond="bj", restart=40, rtol=1e-11)
+    ctx, _ = _case((3, 3, 3), 2, 1.0 / 1600, True, amp=0.05)
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.1)))
+    W1, st = ctx.esdirk3_step(Wg, 0.05, binding.paper_pmg_opts([2, 1]), binding.fgmres_opts(restart=40, rtol=1e-8))
+    err = _rel(W1.cpu().numpy().reshape(Wo.shape), W1o)
+    dif = _rel((W1 - Wg).cpu().numpy().reshape(Wo.shape), W1o - Wo)
+    print("ESDIRK3 p2: newton %d its %d rel_res %.2e err %.2e incr %.2e" % (st.newton, st.linear_iters,
+                                                                          st.max_rel_res_true, err, dif), flush=True)
+    assert st.newton >= 3
+    assert st.max_rel_res_true <= 1e-8
+    assert err < 1e-10 and dif < 1e-6
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_esdirk3_step_p3_paper_config_matches_oracle(mixed, p3_oracle):
+    """The paper's configuration at p = 3 (full multigrid 3 -> 2 -> 1, GMRES(BJ)
+    10/10, coarsest 30, preconditioner lagged over the step; FP64 or mixed)
+    for one ESDIRK3 step against the oracle's ESDIRK3 step (block Jacobi on the
+    oracle side, its blocks at shift 1/(gamma dt) from the fixture's blocks
+    at shift 30 plus the mass matrix): W^{n+1} within 1e-10."""
+    D, W, Dblk30 = p3_oracle
+    a = 1.0 / (ots.ESDIRK3_GAMMA * 0.05)
+    Dblk = Dblk30.copy()
+    for q in range(5):
+        sl = slice(q * D.nv, (q + 1) * D.nv)
+        Dblk[:, sl, sl] += (a - 30.0) * D.M
+    W1o, _ = ots.esdirk3_step(D, W, 0.05, precond="bj", restart=40, rtol=1e-11, Dblk=Dblk)
+    ctx, _, _, Wg = _tgv_case((2, 2, 2), 3, 0.1, 0.1)
+    popts = binding.paper_pmg_opts([3, 2, 1], prec_fine=binding.DG_FP32 if mixed else binding.DG_FP64,
+                                   prec_coarse=binding.DG_BF16 if mixed else binding.DG_FP64)
+    W1, st = ctx.esdirk3_step(Wg, 0.05, popts, binding.fgmres_opts(restart=40, rtol=1e-8))
+    err = _rel(W1.cpu().numpy().reshape(W.shape), W1o)
+    print("ESDIRK3 p3 paper config mixed=%s: newton %d its %d err %.2e" % (mixed, st.newton, st.linear_iters, err),
+          flush=True)
+    assert st.max_rel_res_true <= 1e-8
+    assert err < 1e-10
