@@ -92,10 +92,9 @@ struct Sz {
 };
 // Face phase of the fused kernel (both process the faces in rounds of NQ face
 // points, N whole faces per round, and spread each round onto the Gauss lines):
-//  UP = true:  the neighbour data of all six faces is collapsed and swept up
-//              front; own traces from stored Gauss-point gradients.  Fewer,
-//              longer phases: faster where the registers allow two waves per
-//              SIMD (degree <= 3, real arithmetic).
+//  UP = true:  own traces from stored Gauss-point gradients (45 NQ of LDS:
+//              23 KB at degree 3, seven elements per CU); degree <= 3, real
+//              arithmetic.
 //  UP = false: each round collapses its own faces; own trace gradients from
 //              the face trace (collocation derivative on the face): 40 NQ of
 //              LDS, for degree 4 and the dual-number product.
@@ -105,14 +104,14 @@ template <int P, bool UP>
 struct Lay;
 template <int P>
 struct Lay<P, true> {
-    static constexpr int NQ = Sz<P>::NQ, NF = Sz<P>::NF;
-    // [0, RA): interpolation buffers (15 NQ) | neighbour collapse of all faces (60 NF) |
-    //          face integrands of one round (20 NQ) | test A, B (20 NQ)
-    static constexpr int RA = (20 * NQ > 60 * NF) ? 20 * NQ : 60 * NF;
-    static constexpr int OFF_U = RA;                                       // Gauss values (5 NQ)
+    static constexpr int NQ = Sz<P>::NQ;
+    // [0, 25 NQ): interpolation buffers (15 NQ) | one round: neighbour collapse
+    //             (10 NQ) + first tangential sweep (15 NQ), then face integrands
+    //             (20 NQ) | test A, B (20 NQ)
+    static constexpr int OFF_U = 25 * NQ;                                  // Gauss values (5 NQ)
     static constexpr int OFF_G = OFF_U + 5 * NQ;                           // Gauss ref. gradients (15 NQ)
-    static constexpr int OFF_E = OFF_G + 15 * NQ;                          // tangential sweep (90 NF) | test-back (15 NQ)
-    static constexpr int TOT = OFF_E + ((90 * NF > 15 * NQ) ? 90 * NF : 15 * NQ);
+    static constexpr int OFF_E = OFF_U;                                    // test-back (15 NQ, over the dead values and gradients)
+    static constexpr int TOT = OFF_U + 20 * NQ;
 };
 template <int P>
 struct Lay<P, false> {
@@ -376,83 +375,89 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
     __syncthreads();
 
     if constexpr (UP) {
-        // ---- faces (all neighbour data collapsed up front) ----------------------------
-        T* sC = S;                    // collapse of the neighbour modal data (60 NF)
-        T* sE = S + L_::OFF_E;        // after the first tangential sweep (90 NF)
-        T* sF = S;                    // face integrands of one round (20 NQ; the collapse is dead by then)
-        if (active) {
-            for (int fp = q; fp < 6 * NF; fp += NQ) {
-                const int f = fp / NF, fq = fp % NF;
-                const int d = f >> 1, s = f & 1;
-                const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
-                const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+        // ---- faces --------------------------------------------------------------------
+        // Rounds of NQ face points (N whole faces each, NQ = N NF); thread q takes
+        // slot q = (face fl of the round, face point fq) in every stage:
+        //   1  neighbour: collapse of its modal data along the normal (value and
+        //      normal derivative at the shared face) -> sC;
+        //   2  neighbour: first tangential sweep -> sE;
+        //   3  both traces with reference gradients (own ones from the stored
+        //      Gauss values and gradients), then the face integrand (registers);
+        //   4  integrands -> sF (components 0-9 over sC at once, 10-19 over sE
+        //      after the barrier), spread onto the Gauss lines.
+        // Staging is component-major (sC[c * NQ + slot], ...): consecutive
+        // threads touch consecutive doubles, and only one round's neighbour
+        // data is held at a time.
+        T* sC = S;                    // 10 NQ
+        T* sE = S + 10 * NQ;          // 15 NQ
+        T* sF = S;                    // 20 NQ
+#pragma unroll 1
+        for (int r = 0; r * NQ < 6 * NF; ++r) {
+            const int fp = r * NQ + q;
+            const bool on = active && fp < 6 * NF;
+            const int fl = q / NF, fq = q % NF;
+            const int f = on ? fp / NF : 0;
+            const int d = f >> 1, s = f & 1;
+            const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            const int qt1 = fq / N, qt2 = fq % N;
+            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            const int tl = qt1 * st1 + qt2 * st2;
+            if (on) {
                 const int nb = nbr_of(m, e, f);
                 const size_t nbase = (size_t)nb * NB;
-                const int tb0 = (fq / N) * st1 + (fq % N) * st2;
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
                     T c0 = 0.0, c1 = 0.0;
 #pragma unroll
                     for (int k = 0; k < N; ++k) {
-                        const int pm = perm[tb0 + k * sd];
+                        const int pm = perm[tl + k * sd];
                         const T val = load_state<MODE, T>(W, V, h, nbase + a * NQ + pm);
                         c0 = fma(tb.Le[1 - s][k], val, c0);
                         c1 = fma(tb.Lde[1 - s][k], val, c1);
                     }
-                    sC[(f * NF + fq) * 10 + a * 2 + 0] = c0;
-                    sC[(f * NF + fq) * 10 + a * 2 + 1] = c1;
+                    sC[(a * 2 + 0) * NQ + q] = c0;
+                    sC[(a * 2 + 1) * NQ + q] = c1;
                 }
             }
-        }
-        __syncthreads();
-        if (active) {
-            for (int fp = q; fp < 6 * NF; fp += NQ) {
-                const int f = fp / NF, fq = fp % NF;
-                const int qt1 = fq / N, cc = fq % N;
+            __syncthreads();
+            if (on) {
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
                     T e0 = 0.0, e0d = 0.0, e1 = 0.0;
 #pragma unroll
-                    for (int b = 0; b < N; ++b) {
-                        const T* cb = sC + (f * NF + b * N + cc) * 10 + a * 2;
-                        e0 = fma(tb.V[qt1][b], cb[0], e0);
-                        e0d = fma(tb.Vd[qt1][b], cb[0], e0d);
-                        e1 = fma(tb.V[qt1][b], cb[1], e1);
+                    for (int b2 = 0; b2 < N; ++b2) {
+                        const int src = fl * NF + b2 * N + qt2;
+                        const T cv0 = sC[(a * 2 + 0) * NQ + src];
+                        e0 = fma(tb.V[qt1][b2], cv0, e0);
+                        e0d = fma(tb.Vd[qt1][b2], cv0, e0d);
+                        e1 = fma(tb.V[qt1][b2], sC[(a * 2 + 1) * NQ + src], e1);
                     }
-                    T* eo = sE + (f * NF + fq) * 15 + a * 3;
-                    eo[0] = e0;
-                    eo[1] = e0d;
-                    eo[2] = e1;
+                    sE[(a * 3 + 0) * NQ + q] = e0;
+                    sE[(a * 3 + 1) * NQ + q] = e0d;
+                    sE[(a * 3 + 2) * NQ + q] = e1;
                 }
             }
-        }
-        __syncthreads();
-        for (int r = 0; r * NQ < 6 * NF; ++r) {
-            const int fp = r * NQ + q;
-            if (active && fp < 6 * NF) {
-                const int f = fp / NF, fq = fp % NF;
-                const int d = f >> 1, s = f & 1;
-                const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-                const int qt1 = fq / N, qt2 = fq % N;
-                const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
-                const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            __syncthreads();
+            T fo[20];
+            if (on) {
                 T um[5], gxm[5][3], up[5], gxp[5][3];
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
                     T v0 = 0.0, vt1 = 0.0, vt2 = 0.0, vd = 0.0;
 #pragma unroll
                     for (int c = 0; c < N; ++c) {
-                        const T* eo = sE + (f * NF + qt1 * N + c) * 15 + a * 3;
-                        v0 = fma(tb.V[qt2][c], eo[0], v0);
-                        vt1 = fma(tb.V[qt2][c], eo[1], vt1);
-                        vt2 = fma(tb.Vd[qt2][c], eo[0], vt2);
-                        vd = fma(tb.V[qt2][c], eo[2], vd);
+                        const int src = fl * NF + qt1 * N + c;
+                        const T ev0 = sE[(a * 3 + 0) * NQ + src];
+                        v0 = fma(tb.V[qt2][c], ev0, v0);
+                        vt1 = fma(tb.V[qt2][c], sE[(a * 3 + 1) * NQ + src], vt1);
+                        vt2 = fma(tb.Vd[qt2][c], ev0, vt2);
+                        vd = fma(tb.V[qt2][c], sE[(a * 3 + 2) * NQ + src], vd);
                     }
                     um[a] = v0;
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk) gxm[a][kk] = (kk == d) ? vd : ((kk == t1) ? vt1 : vt2);
                 }
-                const int tl = qt1 * st1 + qt2 * st2;
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
                     T v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -529,24 +534,34 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
                     lam_p = lam_m = 0.5 * N * N * JF / detJ;
                 }
                 face_integrand<T, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
-                                      sF + q * 20);
+                                      fo);
+                // the first ten components go over the (dead) collapse at once
+#pragma unroll
+                for (int k = 0; k < (NS ? 10 : 5); ++k) sF[k * NQ + q] = fo[k];
+            }
+            __syncthreads();
+            if constexpr (NS) {
+                if (on) {
+#pragma unroll
+                    for (int k = 10; k < 20; ++k) sF[k * NQ + q] = fo[k];
+                }
             }
             __syncthreads();
             if (active) {
 #pragma unroll
-                for (int fl = 0; fl < N; ++fl) {
-                    const int f = r * N + fl;
-                    if (f >= 6) break;
-                    const int d = f >> 1, s = f & 1;
-                    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-                    const double l = tb.lag[s][ii[d]];
-                    const T* fo = sF + (fl * NF + ii[t1] * N + ii[t2]) * 20;
+                for (int fl2 = 0; fl2 < N; ++fl2) {
+                    const int f2 = r * N + fl2;
+                    if (f2 >= 6) break;
+                    const int d2 = f2 >> 1, s2 = f2 & 1;
+                    const int u1 = (d2 == 0) ? 1 : 0, u2 = (d2 == 2) ? 1 : 2;
+                    const double l = tb.lag[s2][ii[d2]];
+                    const int src = fl2 * NF + ii[u1] * N + ii[u2];
 #pragma unroll
                     for (int a = 0; a < 5; ++a) {
-                        B[a] = fma(l, fo[a], B[a]);
+                        B[a] = fma(l, sF[a * NQ + src], B[a]);
                         if constexpr (NS) {
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) A[a][k] = fma(l, fo[5 + a * 3 + k], A[a][k]);
+                            for (int k = 0; k < 3; ++k) A[a][k] = fma(l, sF[(5 + a * 3 + k) * NQ + src], A[a][k]);
                         }
                     }
                 }
@@ -894,8 +909,8 @@ __global__ void __launch_bounds__((Launch<P, (MODE >= M_TANGENT)>::EPB * Sz<P>::
     using T = typename std::conditional<DUAL, Dual, double>::type;
     constexpr int EPB = Launch<P, DUAL>::EPB;
     __shared__ T smem[EPB * LayOf<P, MODE>::TOT];
-    __shared__ double sdet[EPB][NQ];
-    __shared__ double svtx[EPB][24];
+    __shared__ double sdet[EPB][CURVED ? NQ : 1];      // curved elements only
+    __shared__ double svtx[EPB][CURVED ? 24 : 1];
     const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
     const int e = blockIdx.x * EPB + es;
     dg_element<P, NS, CURVED, MODE>(m, gas, W, V, RW, hbuf, shift, out, smem + es * LayOf<P, MODE>::TOT, sdet[es],
