@@ -177,12 +177,16 @@ class PMG:
               a V-cycle on each finer level from the prolonged coarser result)."""
 
     def __init__(self, D, W, shift, levels, nu_pre=2, nu_post=2, omega=1.0, coarse_iters=30,
-                 RW=None, Dblk=None, coarse_op="exact", smoother="bj", cycle="v"):
+                 RW=None, Dblk=None, coarse_op="exact", smoother="bj", cycle="v", coarsest_prec="bj"):
         """coarse_op: "exact" applies P^T K_0 P with the exact Jacobian action
         (the inherited operator of Sec. 6.1); "fd" applies P^T K_FD P with the
-        finite-difference product, a matrix-free approximation of it."""
-        assert smoother in ("bj", "gmres") and cycle in ("v", "fmg")
-        self.smoother, self.cycle = smoother, cycle
+        finite-difference product, a matrix-free approximation of it.
+        coarsest_prec: "bj" (element block Jacobi) or "bilu" (block ILU(0) in
+        minimum-discarded-fill order, Sec. 6.3 and Table MGSettings; partitions
+        are the element lines along x, couplings between lines dropped) as the
+        right preconditioner of the coarsest GMRES."""
+        assert smoother in ("bj", "gmres") and cycle in ("v", "fmg") and coarsest_prec in ("bj", "bilu")
+        self.smoother, self.cycle, self.coarsest_prec = smoother, cycle, coarsest_prec
         self.coarse_op = coarse_op
         self.D, self.W, self.shift = D, W, shift
         self.RW = D.residual(W) if RW is None else RW
@@ -195,6 +199,12 @@ class PMG:
         for p in self.levels:
             idx = sub_block_index(nvf, nv_of(p))
             self.blocks.append(lu_factor(Dfine[:, idx][:, :, idx]))
+        self.bilu = None
+        if coarsest_prec == "bilu" and len(self.levels) > 1:
+            cb = coarse_blocks(D, W, shift, self.levels[-1])
+            nx = D.mesh.n[0]
+            part = {e: e // nx for e in range(D.mesh.ne)}
+            self.bilu = BlockILU0(cb, part, mdf_order(cb, part))
 
     def op(self, l, x):
         D = self.D
@@ -224,9 +234,16 @@ class PMG:
                 x = x + self.omega * self.bj(l, b - self.op(l, x))
         return x
 
+    def coarsest_prec_apply(self, r):
+        L = len(self.levels) - 1
+        if self.bilu is None:
+            return self.bj(L, r)
+        z = self.bilu.apply({e: r[e].reshape(-1) for e in range(r.shape[0])})
+        return np.stack([z[e] for e in range(r.shape[0])]).reshape(r.shape)
+
     def coarsest(self, b):
         L = len(self.levels) - 1
-        return gmres_fixed(lambda x: self.op(L, x), lambda r: self.bj(L, r), b, self.coarse_iters)
+        return gmres_fixed(lambda x: self.op(L, x), self.coarsest_prec_apply, b, self.coarse_iters)
 
     def vcycle(self, l, b, x=None):
         """Alg. 2 MG_V(l, b, x); x = None is the zero initial guess."""
@@ -391,3 +408,160 @@ def fgmres(A, prec, b, restart, rtol, max_restarts=20, x0=None):
             return x, st
         st.restarts += 1
     return x, st
+
+
+# ---- assembled inherited coarse operator (Sec. 6.1) ---------------------------------
+def distance2_colouring(mesh):
+    """Greedy colouring in which no two elements of one colour are face
+    neighbours or share a face neighbour."""
+    near = []
+    for e in range(mesh.ne):
+        s = {e} | set(int(o) for o in mesh.nbr[e])
+        for o in list(s):
+            s |= set(int(x) for x in mesh.nbr[o])
+        near.append(s)
+    col = -np.ones(mesh.ne, dtype=np.int64)
+    for e in range(mesh.ne):
+        used = {col[o] for o in near[e] if col[o] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[e] = c
+    return col
+
+
+def coarse_blocks(D, W, shift, pc):
+    """Blocks of the inherited operator K_l = P^T K_0 P (Sec. 6.1) of degree pc,
+    K_0 = shift M + dR/dW at W: {(i, j): block}, rows of element i and columns
+    of element j over the coarse modes (equation-major, as W[e, a, i]), for
+    j = i and j a face neighbour of i.  Column c of every block comes from the
+    complex-step derivative of R for the coarse DOF c of all elements of one
+    distance-2 colour class at once (no row element sees two perturbed
+    elements)."""
+    mesh = D.mesh
+    nvc = nv_of(pc)
+    nbc = 5 * nvc
+    rows = sub_block_index(D.nv, nvc)
+    col = distance2_colouring(mesh)
+    blocks = {}
+    for e in range(mesh.ne):
+        blocks[(e, e)] = np.zeros((nbc, nbc))
+        for o in mesh.nbr[e]:
+            if o != e:
+                blocks[(int(o), e)] = np.zeros((nbc, nbc))
+    for c in range(col.max() + 1):
+        sel = np.nonzero(col == c)[0]
+        for j in range(nbc):
+            a, i = divmod(j, nvc)
+            Wc = W.astype(complex)
+            Wc[sel, a, i] += 1j * H_CS
+            Rc = (np.imag(D.residual(Wc)) / H_CS).reshape(mesh.ne, -1)[:, rows]
+            for e in sel:
+                blocks[(e, e)][:, j] = Rc[e]
+                for o in set(int(x) for x in mesh.nbr[e]):
+                    if o != e:
+                        blocks[(o, e)][:, j] = Rc[o]
+    Msub = D.M[:, :nvc, :nvc]
+    for e in range(mesh.ne):
+        for a in range(5):
+            blocks[(e, e)][a * nvc:(a + 1) * nvc, a * nvc:(a + 1) * nvc] += shift * Msub[e]
+    return blocks
+
+
+# ---- block ILU(0) with minimum-discarded-fill ordering (Sec. 6.3) --------------------
+# A block matrix on the element graph is held as a dict {(i, j): nb x nb array}
+# with (i, i) the diagonal blocks and (i, j), j a face neighbour of i, the
+# coupling blocks (row block i, column block j).  `part[i]` names the
+# partition of element i: the factorisation is done on each partition's
+# square block of the matrix, couplings between partitions are dropped (the
+# partition-wise "BILU" of Sec. 6.3).
+
+def block_pattern(blocks):
+    """Neighbour sets {i: set(j)} of the off-diagonal blocks present."""
+    nbr = {}
+    for (i, j) in blocks:
+        nbr.setdefault(i, set())
+        if i != j:
+            nbr[i].add(j)
+    return nbr
+
+
+def discarded_fill(blocks, nbr, k, alive):
+    """Frobenius norm of the fill that eliminating k discards in ILU(0): the
+    blocks A_jk A_kk^-1 A_kl for ordered pairs j != l of k's neighbours still
+    to be eliminated whose (j, l) block is not in the pattern (Persson &
+    Peraire's minimum-discarded-fill weight), on the unfactored blocks."""
+    Dinv = np.linalg.inv(blocks[(k, k)])
+    js = [j for j in sorted(nbr[k]) if j in alive]
+    w = 0.0
+    for j in js:
+        for l in js:
+            if j != l and l not in nbr[j]:
+                w += float(np.sum((blocks[(j, k)] @ Dinv @ blocks[(k, l)]) ** 2))
+    return np.sqrt(w)
+
+
+def mdf_order(blocks, part):
+    """Minimum-discarded-fill ordering within each partition: repeatedly
+    eliminate the element whose elimination discards the least fill (ties:
+    the lowest element index).  Returns the elements in elimination order
+    (partitions one after another, in increasing partition id)."""
+    nbr_all = block_pattern(blocks)
+    order = []
+    for pid in sorted(set(part.values())):
+        elems = [i for i in sorted(part) if part[i] == pid]
+        nbr = {i: {j for j in nbr_all[i] if part[j] == pid} for i in elems}
+        alive = set(elems)
+        while alive:
+            best = min(sorted(alive), key=lambda k: (discarded_fill(blocks, nbr, k, alive), k))
+            order.append(best)
+            alive.remove(best)
+    return order
+
+
+class BlockILU0:
+    """Block ILU(0) of the partition-wise blocks in a given elimination order
+    (Sec. 6.3): for each k in order, L_jk = A_jk A_kk^-1 for the later
+    neighbours j of k, and A_jl -= L_jk A_kl for later neighbours j, l of k
+    whenever (j, l) is in the pattern (j == l included); other fill is
+    discarded.  U keeps the updated blocks A_kk and A_kl (l later than k).
+    apply(r) solves L U z = r by a forward sweep in order and a backward
+    sweep in reverse order.  r and z are dicts {element: vector}."""
+
+    def __init__(self, blocks, part, order):
+        self.part = part
+        self.order = list(order)
+        self.pos = {k: i for i, k in enumerate(self.order)}
+        nbr_all = block_pattern(blocks)
+        self.nbr = {i: {j for j in nbr_all[i] if part[j] == part[i]} for i in part}
+        A = {key: np.array(v, dtype=float, copy=True) for key, v in blocks.items()
+             if part[key[0]] == part[key[1]]}
+        self.L = {}
+        for k in self.order:
+            Dinv = np.linalg.inv(A[(k, k)])
+            later = sorted(j for j in self.nbr[k] if self.pos[j] > self.pos[k])
+            for j in later:
+                self.L[(j, k)] = A[(j, k)] @ Dinv
+            for j in later:
+                for l in later:
+                    if j == l or l in self.nbr[j]:
+                        A[(j, l)] = A[(j, l)] - self.L[(j, k)] @ A[(k, l)]
+        self.U = {(k, l): A[(k, l)] for k in self.order for l in [k] + sorted(self.nbr[k])
+                  if self.pos[l] >= self.pos[k]}
+
+    def apply(self, r):
+        y = {}
+        for k in self.order:
+            v = np.array(r[k], dtype=float, copy=True)
+            for j in self.nbr[k]:
+                if self.pos[j] < self.pos[k]:
+                    v -= self.L[(k, j)] @ y[j]
+            y[k] = v
+        z = {}
+        for k in reversed(self.order):
+            v = y[k].copy()
+            for l in self.nbr[k]:
+                if self.pos[l] > self.pos[k]:
+                    v -= self.U[(k, l)] @ z[l]
+            z[k] = np.linalg.solve(self.U[(k, k)], v)
+        return z
