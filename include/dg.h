@@ -185,6 +185,21 @@ dg_status dg_mass(dg_ctx* ctx, const double* v, double* y);
  * i = equation * (p+1)^3 + mode. */
 dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* blocks);
 
+/* dg_assemble_diag without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and result as
+ * dg_assemble_diag (bit for bit), but the neighbour traces it stages
+ * (ne * 6 (p+1)^2 * 20 doubles) live in a fixed 128 MiB device array that the
+ * library holds on every GPU it runs on until the process ends, instead of
+ * context memory allocated on first use; the call makes no allocation.
+ * Meshes whose traces exceed 128 MiB (above 5,592 elements at p = 4, i.e.
+ * beyond 17^3; above 8,738 at p = 3, beyond 20^3) are rejected with DG_EINVAL
+ * before any GPU work.  All calls
+ * on one GPU share the array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.  Enqueued on
+ * the context's stream. */
+dg_status dg_assemble_diag_noalloc(dg_ctx* ctx, const double* W, double shift, double* blocks);
+
 /* Face-coupling blocks of the inherited coarse operator of degree pc
  * (Sec. 6.1, K_l = P^T K_0 P; 1 <= pc <= p, pc = p giving the face blocks of
  * the fine operator itself): off [ne][6][nbc][nbc], nbc =

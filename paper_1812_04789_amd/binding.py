@@ -102,6 +102,7 @@ SIGNATURES = {
     "dg_jvp_exact": (_I, [_P, _P, _P, _D, _P]),
     "dg_mass": (_I, [_P, _P, _P]),
     "dg_assemble_diag": (_I, [_P, _P, _D, _P]),
+    "dg_assemble_diag_noalloc": (_I, [_P, _P, _D, _P]),
     "dg_assemble_coarse": (_I, [_P, _P, _I, _P]),
     "dg_assemble_operator": (_I, [_P, _P, _D]),
     "dg_jvp_assembled": (_I, [_P, _P, _P]),
@@ -337,6 +338,14 @@ class Context:
         nb = 5 * self.nv
         out = self.empty(self.ne * nb * nb)
         self._check(self.lib.dg_assemble_diag(self.h, self._vec(W, "W"), float(shift), _ptr(out)))
+        return out.view(self.ne, nb, nb)       # [e][col][row]
+
+    def assemble_diag_noalloc(self, W, shift, out):
+        """dg_assemble_diag_noalloc into the caller's float64 tensor `out`
+        (ne * nb * nb entries): the library allocates nothing."""
+        nb = 5 * self.nv
+        self._check(self.lib.dg_assemble_diag_noalloc(self.h, self._vec(W, "W"), float(shift),
+                                                      self._vec(out, "out", self.ne * nb * nb)))
         return out.view(self.ne, nb, nb)       # [e][col][row]
 
     def assemble_coarse(self, W, pc):

@@ -110,6 +110,15 @@ Tab g_tabs[MAXP + 1];
 short g_perm[PERM_TOTAL];
 bool g_tab_uploaded[64] = {false};
 
+// Scratch of dg_assemble_diag_noalloc: the neighbour traces at the face points
+// (nbr_trace_size(p, ne) doubles), in a file-scope device array of fixed size
+// that every GPU the library runs on holds until the process ends.  Host code
+// never uses `scratch` directly: its device address on each device is
+// resolved once (dg_create, with that device current) into g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)16 << 20;        // 128 MiB
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+double* g_scratch_ptr[64] = {nullptr};                              // guarded by g_tab_mu
+
 }  // namespace
 
 struct dg_ctx {
@@ -1021,6 +1030,11 @@ dg_status dg_create(const dg_mesh_desc* mesh, const dg_phys* phys, int p, void* 
                 CK(upload_tables(g_tabs, g_perm));
                 g_tab_uploaded[ctx->device] = true;
             }
+            if (!g_scratch_ptr[ctx->device]) {
+                void* ptr = nullptr;
+                CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+                g_scratch_ptr[ctx->device] = static_cast<double*>(ptr);
+            }
         }
         ctx->s = (hipStream_t)hip_stream;
         ctx->p = p;
@@ -1173,6 +1187,25 @@ dg_status dg_assemble_diag(dg_ctx* ctx, const double* W, double shift, double* b
         need(ctx, blocks, "blocks");
         ctx->nbrtr.ensure(nbr_trace_size(ctx->p, ctx->ne));
         CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->nb, ctx->nbrtr.p, ctx->s));
+    });
+}
+
+dg_status dg_assemble_diag_noalloc(dg_ctx* ctx, const double* W, double shift, double* blocks) {
+    return guarded(ctx, [&] {
+        need(ctx, W, "W");
+        need(ctx, blocks, "blocks");
+        if (nbr_trace_size(ctx->p, ctx->ne) > NOALLOC_SCRATCH_DOUBLES)
+            fail(ctx, DG_EINVAL, "mesh too large for dg_assemble_diag_noalloc: its neighbour traces need " +
+                                     std::to_string(nbr_trace_size(ctx->p, ctx->ne) * sizeof(double)) +
+                                     " bytes, the fixed scratch holds " +
+                                     std::to_string(NOALLOC_SCRATCH_DOUBLES * sizeof(double)));
+        double* ws = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_tab_mu);
+            ws = g_scratch_ptr[ctx->device];
+        }
+        if (!ws) fail(ctx, DG_ESTATE, "scratch address not resolved on this device");
+        CK(launch_diag_blocks(ctx->a, W, shift, blocks, ctx->nb, ws, ctx->s));
     });
 }
 
