@@ -110,7 +110,15 @@ typedef struct {
  *  cycle          0 = one V-cycle from zero (Alg. 2); 1 = the full multigrid
  *                 cycle of Alg. 1 (the level-0 right-hand side restricted to
  *                 every level, the coarsest level solved, then one V-cycle on
- *                 each finer level from the prolonged coarser result). */
+ *                 each finer level from the prolonged coarser result).
+ *  coarsest_prec  right preconditioner of the coarsest GMRES: 0 = element
+ *                 block Jacobi; 1 = block ILU(0) in minimum-discarded-fill
+ *                 order (Sec. 6.3, Table MGSettings), partition-wise with the
+ *                 element lines along x as partitions (couplings between
+ *                 lines dropped), factors FP64, factored once per pmg_setup
+ *                 (which then synchronises the stream: the elimination order
+ *                 is chosen on the host).  Needs an assembled degree-1
+ *                 coarsest level (n_levels >= 2, coarse_matrix_free 0 or 2). */
 typedef struct {
     int n_levels;
     int p_level[4];
@@ -123,6 +131,7 @@ typedef struct {
     int coarsest_plain;
     int smoother;
     int cycle;
+    int coarsest_prec;
 } pmg_opts;
 
 /* FGMRES(restart) (Sec. 6), restart 1..63: x0 = 0, converged when the recomputed true

@@ -501,11 +501,16 @@ def discarded_fill(blocks, nbr, k, alive):
     return np.sqrt(w)
 
 
+MDF_TIE = 1e-10
+
+
 def mdf_order(blocks, part):
     """Minimum-discarded-fill ordering within each partition: repeatedly
-    eliminate the element whose elimination discards the least fill (ties:
-    the lowest element index).  Returns the elements in elimination order
-    (partitions one after another, in increasing partition id)."""
+    eliminate the element whose elimination discards the least fill.  Ties
+    (weights within a relative MDF_TIE of the smallest, so that rounding of
+    the weights does not decide) go to the lowest element index.  Returns the
+    elements in elimination order (partitions one after another, in
+    increasing partition id)."""
     nbr_all = block_pattern(blocks)
     order = []
     for pid in sorted(set(part.values())):
@@ -513,7 +518,9 @@ def mdf_order(blocks, part):
         nbr = {i: {j for j in nbr_all[i] if part[j] == pid} for i in elems}
         alive = set(elems)
         while alive:
-            best = min(sorted(alive), key=lambda k: (discarded_fill(blocks, nbr, k, alive), k))
+            w = {k: discarded_fill(blocks, nbr, k, alive) for k in alive}
+            wmin = min(w.values())
+            best = min(k for k in alive if w[k] <= wmin * (1.0 + MDF_TIE))
             order.append(best)
             alive.remove(best)
     return order

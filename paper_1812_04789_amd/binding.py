@@ -33,7 +33,8 @@ class PmgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("p_level", ctypes.c_int * 4), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("coarsest_iters", ctypes.c_int),
                 ("prec_fine", ctypes.c_int), ("prec_coarse", ctypes.c_int), ("coarse_matrix_free", ctypes.c_int),
-                ("coarsest_plain", ctypes.c_int), ("smoother", ctypes.c_int), ("cycle", ctypes.c_int)]
+                ("coarsest_plain", ctypes.c_int), ("smoother", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("coarsest_prec", ctypes.c_int)]
 
 
 class FgmresOpts(ctypes.Structure):
@@ -187,26 +188,30 @@ class DGError(RuntimeError):
 
 SMOOTH_BJ, SMOOTH_GMRES = 0, 1
 CYCLE_V, CYCLE_FMG = 0, 1
+COARSEST_BJ, COARSEST_BILU = 0, 1
 
 
 def pmg_opts(levels, nu_pre=2, nu_post=2, omega=1.0, coarsest_iters=30, prec_fine=DG_FP64,
-             prec_coarse=DG_FP64, coarse_matrix_free=1, coarsest_plain=0, smoother=SMOOTH_BJ, cycle=CYCLE_V):
+             prec_coarse=DG_FP64, coarse_matrix_free=1, coarsest_plain=0, smoother=SMOOTH_BJ, cycle=CYCLE_V,
+             coarsest_prec=COARSEST_BJ):
     o = PmgOpts()
     o.n_levels = len(levels)
     for i, p in enumerate(levels):
         o.p_level[i] = int(p)
     o.nu_pre, o.nu_post, o.omega, o.coarsest_iters = nu_pre, nu_post, omega, coarsest_iters
     o.prec_fine, o.prec_coarse, o.coarse_matrix_free = prec_fine, prec_coarse, coarse_matrix_free
-    o.coarsest_plain, o.smoother, o.cycle = coarsest_plain, smoother, cycle
+    o.coarsest_plain, o.smoother, o.cycle, o.coarsest_prec = coarsest_plain, smoother, cycle, coarsest_prec
     return o
 
 
-def paper_pmg_opts(levels, prec_fine=DG_FP64, prec_coarse=DG_FP64, coarse_matrix_free=2):
+def paper_pmg_opts(levels, prec_fine=DG_FP64, prec_coarse=DG_FP64, coarse_matrix_free=2, coarsest_prec=COARSEST_BJ):
     """The paper's preconditioner (Sec. 6, Alg. 1, Table MGSettings): full
     multigrid, GMRES(BJ) smoothers with 10 iterations on the finer levels, a
-    30-iteration coarsest GMRES (block Jacobi in place of the paper's BILU)."""
+    30-iteration coarsest GMRES preconditioned by block Jacobi or (as in the
+    table) by block ILU(0) in minimum-discarded-fill order."""
     return pmg_opts(levels, nu_pre=10, nu_post=10, coarsest_iters=30, prec_fine=prec_fine, prec_coarse=prec_coarse,
-                    coarse_matrix_free=coarse_matrix_free, smoother=SMOOTH_GMRES, cycle=CYCLE_FMG)
+                    coarse_matrix_free=coarse_matrix_free, smoother=SMOOTH_GMRES, cycle=CYCLE_FMG,
+                    coarsest_prec=coarsest_prec)
 
 
 def fgmres_opts(restart=30, rtol=1e-8, max_restarts=20, jvp_exact=1):

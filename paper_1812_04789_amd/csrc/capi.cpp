@@ -93,6 +93,9 @@ struct Level {
     DBuf<float> inv32;
     DBuf<double> x, b, r, t, z;
     DBuf<double> fb, fx;       // full multigrid: this level's restricted right-hand side and iterate
+    bool bilu = false;         // coarsest level preconditioned by block ILU(0) (element lines along x)
+    DBuf<double> bd, bo, bw;   // block ILU(0): inverses of the updated diagonal blocks, L/U line blocks, MDF weights
+    DBuf<int> bord, bpos;      // each line's elimination order and every element's position in it
     // assembled inherited operator: diagonal + 6 face blocks per element
     bool assembled = false;
     int op_prec = DG_FP64;
@@ -101,7 +104,8 @@ struct Level {
     DBuf<unsigned short> op16;
     void release() { inv64.release(); inv32.release(); op64.release(); op32.release(); op16.release();
                      f64.release(); f32.release(); piv.release(); pos.release(); x.release(); b.release(); r.release(); t.release(); z.release();
-                     fb.release(); fx.release(); }
+                     fb.release(); fx.release(); bd.release(); bo.release(); bw.release(); bord.release();
+                     bpos.release(); }
 };
 
 std::mutex g_tab_mu;
@@ -272,6 +276,20 @@ void level_op(dg_ctx* ctx, int l, const double* x, double* y) {
 
 void gmres_fixed_dev(dg_ctx* ctx, int l, Krylov& K, const double* b, double* x, int iters);
 
+// Right preconditioner of a level's GMRES: block ILU(0) on a coarsest level
+// that has it, element block Jacobi otherwise.
+void level_prec(dg_ctx* ctx, int l, const double* r, double* z) {
+    Level& L = ctx->lv[l];
+    if (!L.bilu) {
+        bj_apply(ctx, l, r, z);
+        return;
+    }
+    const double nbl = L.nb;
+    timed(ctx, DG_K_BJ_COARSE, ctx->ne * (5.0 * 8.0 * nbl * nbl + 16.0 * nbl), ctx->ne * 10.0 * nbl * nbl, [&] {
+        return launch_bilu_apply(ctx->a, L.nb, L.bord.p, L.bpos.p, L.bd.p, L.bo.p, r, z, ctx->s);
+    });
+}
+
 // SMOOTH of Alg. 2 on level l: nu damped block-Jacobi sweeps, or (smoother =
 // 1) nu iterations of right-preconditioned GMRES(BJ) on the residual
 // equation, x <- x + GMRES(K_l, D_l^-1, b - K_l x).
@@ -385,7 +403,7 @@ void gmres_fixed_dev(dg_ctx* ctx, int l, Krylov& K, const double* b, double* x, 
     CK(launch_scale_dev(n, b, K.g.p, 1, K.V.p, ctx->s));
     for (int j = 0; j < iters; ++j) {
         double* z = K.Z.p + (size_t)j * n;
-        bj_apply(ctx, l, K.V.p + (size_t)j * n, z);
+        level_prec(ctx, l, K.V.p + (size_t)j * n, z);
         level_op(ctx, l, z, K.V.p + (size_t)(j + 1) * n);
         arnoldi_orth(ctx, K, j, n);
     }
@@ -505,6 +523,14 @@ void check_pmg_opts(dg_ctx* ctx, const pmg_opts* o) {
     if (o->cycle != 0 && o->cycle != 1) fail(ctx, DG_EINVAL, "cycle must be 0 (V-cycle) or 1 (full multigrid)");
     if (o->smoother == 1 && (o->nu_pre > 63 || o->nu_post > 63))
         fail(ctx, DG_EINVAL, "GMRES smoother iterations must be at most 63");
+    if (o->coarsest_prec != 0 && o->coarsest_prec != 1) fail(ctx, DG_EINVAL, "coarsest_prec must be 0 (BJ) or 1 (BILU)");
+    if (o->coarsest_prec == 1) {
+        if (o->n_levels < 2 || o->coarse_matrix_free == 1)
+            fail(ctx, DG_EINVAL, "BILU needs an assembled coarsest level (n_levels >= 2, coarse_matrix_free 0 or 2)");
+        const int pc = o->p_level[o->n_levels - 1];
+        if (5 * (pc + 1) * (pc + 1) * (pc + 1) > BILU_MAX_N)
+            fail(ctx, DG_EINVAL, "BILU supports a degree-1 coarsest level only");
+    }
 }
 
 double lu_bytes(dg_ctx* ctx, int nb, double s) { return ctx->ne * 2.0 * s * (double)nb * nb; }
@@ -545,6 +571,31 @@ void form_inverse(dg_ctx* ctx, Level& L, double* ws) {
     L.inv_done = true;
 }
 
+// Block ILU(0) of the coarsest level from its unpacked FP64 blocks (diagonal
+// in dtmp, face blocks in otmp): line couplings gathered, minimum-discarded-
+// fill weights on the device, each line's order on the host, then the
+// in-place factorisation, one workgroup per line.
+void bilu_setup(dg_ctx* ctx, Level& L) {
+    const size_t nn = (size_t)L.nb * L.nb;
+    const MeshDev& m = ctx->a.m;
+    L.bd.ensure(ctx->ne * nn);
+    L.bo.ensure(2 * ctx->ne * nn);
+    L.bw.ensure(ctx->ne);
+    L.bord.ensure(ctx->ne);
+    L.bpos.ensure(ctx->ne);
+    CK(launch_bilu_gather(ctx->a, L.nb, ctx->dtmp.p, ctx->otmp.p, L.bd.p, L.bo.p, ctx->s));
+    CK(launch_bilu_weights(ctx->a, L.nb, L.bd.p, L.bo.p, L.bw.p, ctx->s));
+    std::vector<double> w(ctx->ne);
+    std::vector<int> ord(ctx->ne), pos(ctx->ne);
+    CK(hipMemcpyAsync(w.data(), L.bw.p, ctx->ne * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    CK(hipStreamSynchronize(ctx->s));
+    bilu_mdf_order(m.nx, m.ny, m.nz, w.data(), ord.data(), pos.data());
+    CK(hipMemcpyAsync(L.bord.p, ord.data(), ctx->ne * sizeof(int), hipMemcpyHostToDevice, ctx->s));
+    CK(hipMemcpyAsync(L.bpos.p, pos.data(), ctx->ne * sizeof(int), hipMemcpyHostToDevice, ctx->s));
+    CK(launch_bilu_factor(ctx->a, L.nb, L.bord.p, L.bpos.p, L.bd.p, L.bo.p, ctx->s));
+    CK(hipStreamSynchronize(ctx->s));                 // the host order arrays go out of scope
+}
+
 void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* o) {
     check_pmg_opts(ctx, o);
     ctx->pmg_ready = false;
@@ -576,7 +627,9 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
         L.op_prec = o->prec_coarse;
         L.inv = L.nb <= INV_POLICY_N;
         L.inv_done = false;
-        L.fold = L.assembled && l == o->n_levels - 1 && L.inv && L.nb <= FOLD_MAX_N && o->coarsest_plain == 0;
+        L.bilu = L.assembled && l == o->n_levels - 1 && o->coarsest_prec == 1;
+        L.fold = L.assembled && l == o->n_levels - 1 && L.inv && L.nb <= FOLD_MAX_N && o->coarsest_plain == 0 &&
+                 !L.bilu;
         L.piv.ensure((size_t)ctx->ne * L.nb);
         L.pos.ensure((size_t)ctx->ne * L.nb);
         L.x.ensure(L.ndof);
@@ -596,6 +649,7 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
             CK(launch_extract_sub<double>(ctx->blk.p, nb, ld0, ctx->nv, L.nv, ctx->dtmp.p, ctx->ne, ctx->s));
             CK(launch_offdiag_blocks(ctx->a, ctx->W0.p, L.p, ctx->otmp.p, ctx->s));
             if (!L.fold) pack_operator(ctx, L, 7);
+            if (L.bilu) bilu_setup(ctx, L);
         }
         if (L.use32) {
             const size_t szl = (size_t)ctx->ne * L.nb * L.ld;
@@ -647,6 +701,10 @@ void pmg_setup_impl(dg_ctx* ctx, const double* W, double shift, const pmg_opts* 
     }
     for (size_t l = (o->smoother == 1 ? (size_t)std::max(0, o->n_levels - 1) : 0); l < ctx->ks.size(); ++l)
         ctx->ks[l].release();
+    for (Level& L : ctx->lv)
+        if (!L.bilu) {
+            L.bd.release(); L.bo.release(); L.bw.release(); L.bord.release(); L.bpos.release();
+        }
     // full multigrid: restricted right-hand sides and iterates of the coarse levels
     for (int l = 1; l < o->n_levels; ++l) {
         Level& L = ctx->lv[l];
@@ -944,7 +1002,8 @@ extern "C" double dg_device_bytes(const dg_ctx* ctx) {
     for (const Level& L : ctx->lv)
         b += bytes_of(L.f64) + bytes_of(L.f32) + bytes_of(L.piv) + bytes_of(L.pos) + bytes_of(L.inv64) +
              bytes_of(L.inv32) + bytes_of(L.x) + bytes_of(L.b) + bytes_of(L.r) + bytes_of(L.t) + bytes_of(L.z) +
-             bytes_of(L.op64) + bytes_of(L.op32) + bytes_of(L.op16) + bytes_of(L.fb) + bytes_of(L.fx);
+             bytes_of(L.op64) + bytes_of(L.op32) + bytes_of(L.op16) + bytes_of(L.fb) + bytes_of(L.fx) +
+             bytes_of(L.bd) + bytes_of(L.bo) + bytes_of(L.bw) + bytes_of(L.bord) + bytes_of(L.bpos);
     return b;
 }
 
@@ -967,9 +1026,10 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
         const bool assembled = l > 0 && (po->coarse_matrix_free == 0 ||
                                          (po->coarse_matrix_free == 2 && l == po->n_levels - 1));
         const bool fold = assembled && l == po->n_levels - 1 && nbl <= INV_POLICY_N && nbl <= FOLD_MAX_N &&
-                          po->coarsest_plain == 0;
+                          po->coarsest_plain == 0 && po->coarsest_prec == 0;
         b += 2 * ndl * 4 + 5 * ndl * 8;                                           // pivots, positions, vectors
         if (po->cycle == 1 && l > 0) b += 2 * ndl * 8;                           // full multigrid b_l, x_l
+        if (po->coarsest_prec == 1 && l == po->n_levels - 1) b += 3 * sz * 8 + ne * 16;   // block ILU(0)
         if (po->smoother == 1 && l < po->n_levels - 1)                            // GMRES(BJ) smoother
             b += krylov(std::max(1, std::max(po->nu_pre, po->nu_post)), ndl);
         if (assembled) {
@@ -990,7 +1050,7 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
             const int pl = po->p_level[l];
             const double nbl = 5.0 * (pl + 1) * (pl + 1) * (pl + 1);
             const bool fold = l == po->n_levels - 1 && nbl <= FOLD_MAX_N && po->coarsest_plain == 0 &&
-                              (po->coarse_matrix_free == 0 || po->coarse_matrix_free == 2);
+                              po->coarsest_prec == 0 && (po->coarse_matrix_free == 0 || po->coarse_matrix_free == 2);
             if (po->prec_coarse != DG_FP64 && nbl <= INV_POLICY_N && !fold) ws = std::max(ws, ne * nbl * nbl * 8);
         }
         b += ws;

@@ -211,6 +211,24 @@ constexpr int FOLD_MAX_N = 64;
 template <class TX>
 hipError_t launch_fold_inverse(const DGArgs& a, int nbc, double* off, const TX* X, hipStream_t s);
 hipError_t launch_convert_fp64_to_fp32(const double* x, float* y, size_t n, hipStream_t s);
+
+// ---- block ILU(0) of the coarsest level, element lines along x (bilu.hip) -------
+constexpr int BILU_MAX_N = 48;
+// d [ne][nb^2] <- diag, o [ne][2][nb^2] <- the couplings to the two line
+// neighbours from the face blocks off [ne][6][nb^2] (column-major blocks).
+hipError_t launch_bilu_gather(const DGArgs& a, int nb, const double* diag, const double* off, double* d, double* o,
+                              hipStream_t s);
+// w[e]: minimum-discarded-fill weight of eliminating e with both line
+// neighbours remaining (0 for lines of fewer than four elements).
+hipError_t launch_bilu_weights(const DGArgs& a, int nb, const double* d, const double* o, double* w, hipStream_t s);
+// Host: each line's elimination order ord[line * nx + t] and pos[e] from w.
+void bilu_mdf_order(int nx, int ny, int nz, const double* w, int* ord, int* pos);
+// In-place block ILU(0) of every line (d <- inverses of the updated diagonal
+// blocks, o <- L or U blocks); z = (L U)^-1 r.
+hipError_t launch_bilu_factor(const DGArgs& a, int nb, const int* ord, const int* pos, double* d, double* o,
+                              hipStream_t s);
+hipError_t launch_bilu_apply(const DGArgs& a, int nb, const int* ord, const int* pos, const double* d,
+                             const double* o, const double* r, double* z, hipStream_t s);
 hipError_t launch_convert_fp64_to_bf16(const double* x, unsigned short* y, size_t n, hipStream_t s);
 
 }  // namespace dg

@@ -36,12 +36,12 @@ struct Key {
     int nx, ny, nz, p;
     double lo[3], hi[3];
     double gamma, mu, Pr, eta;
-    int levels[5], prec_fine, prec_coarse, cmf, cplain, smoother, cycle, nu, citers, restart;
+    int levels[5], prec_fine, prec_coarse, cmf, cplain, smoother, cycle, nu, cprec, citers, restart;
     bool operator==(const Key& o) const {
         return nx == o.nx && ny == o.ny && nz == o.nz && p == o.p && std::equal(lo, lo + 3, o.lo) &&
                std::equal(hi, hi + 3, o.hi) && gamma == o.gamma && mu == o.mu && Pr == o.Pr && eta == o.eta &&
                std::equal(levels, levels + 5, o.levels) && prec_fine == o.prec_fine && prec_coarse == o.prec_coarse &&
-               cmf == o.cmf && cplain == o.cplain && smoother == o.smoother && cycle == o.cycle && nu == o.nu &&
+               cmf == o.cmf && cplain == o.cplain && smoother == o.smoother && cycle == o.cycle && nu == o.nu && cprec == o.cprec &&
                citers == o.citers && restart == o.restart;
     }
 };
@@ -82,6 +82,7 @@ Key key_of(const dg_request& r) {
     k.cplain = r.popts.coarsest_plain;
     k.smoother = r.popts.smoother;
     k.cycle = r.popts.cycle;
+    k.cprec = r.popts.coarsest_prec;
     k.nu = r.popts.smoother == 1 ? std::max(r.popts.nu_pre, r.popts.nu_post) : 0;
     k.citers = r.popts.coarsest_iters;
     k.restart = r.fopts.restart;

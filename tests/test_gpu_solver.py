@@ -511,3 +511,53 @@ def test_esdirk3_step_p3_paper_config_matches_oracle(mixed, p3_oracle):
           flush=True)
     assert st.max_rel_res_true <= 1e-8
     assert err < 1e-10
+
+
+# ---- block ILU(0) with minimum-discarded-fill order on the coarsest level --------------
+@pytest.mark.parametrize("n", [(4, 2, 2), (3, 2, 2), (2, 3, 2)])
+def test_vcycle_with_bilu_coarsest_matches_oracle(n):
+    """A two-level V-cycle 2 -> 1 whose coarsest GMRES is preconditioned by
+    block ILU(0) on the element lines along x in minimum-discarded-fill order
+    (Sec. 6.3, Table MGSettings) against the oracle's (lines of four with
+    discarded fill, of three with the wrap coupling kept, of two): 1e-5.  A
+    small shift and three coarsest steps keep the coarse solve partial, so
+    the result depends on the preconditioner (block Jacobi there differs by
+    far more)."""
+    ctx, D = _case(n, 2, 0.02, True)
+    W = inputs.random_state(ctx.ne, 2, seed=111)
+    r = inputs.random_vector(ctx.ne, 2, seed=112)
+    a = 1.0
+    ctx.pmg_setup(_dev(W), a, binding.pmg_opts([2, 1], coarsest_iters=3, coarse_matrix_free=0,
+                                               coarsest_prec=binding.COARSEST_BILU))
+    z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(r.shape)
+    zo = olin.PMG(D, W, a, [2, 1], coarse_iters=3, coarse_op="exact", coarsest_prec="bilu").apply(r)
+    err = _rel(z, zo)
+    zb = olin.PMG(D, W, a, [2, 1], coarse_iters=3, coarse_op="exact", coarsest_prec="bj").apply(r)
+    print("BILU coarsest %s rel err %.2e (BJ differs by %.2e)" % (n, err, _rel(zb, zo)), flush=True)
+    assert err < 1e-5
+    assert _rel(zb, zo) > 100 * err
+
+
+def test_bilu_needs_an_assembled_degree_one_coarsest_level():
+    ctx, _ = _case((2, 2, 2), 2, 0.02, False)
+    W = _dev(inputs.random_state(ctx.ne, 2, seed=113))
+    for opts in (binding.pmg_opts([2], coarsest_prec=binding.COARSEST_BILU),
+                 binding.pmg_opts([2, 1], coarse_matrix_free=1, coarsest_prec=binding.COARSEST_BILU)):
+        with pytest.raises(binding.DGError) as ei:
+            ctx.pmg_setup(W, 10.0, opts)
+        assert ei.value.status == binding.DG_EINVAL
+
+
+def test_bdf2_step_paper_preconditioner_with_bilu_matches_oracle(tgv_oracle):
+    """The paper's preconditioner complete (full multigrid, GMRES(BJ) 10/10
+    smoothers, coarsest GMRES(BILU) 30) in a BDF2 step of the curved p = 2
+    Taylor-Green case: W^{n+1} within 1e-10 of the oracle's."""
+    D, Wo, W1o = tgv_oracle
+    ctx, _ = _case((3, 3, 3), 2, 1.0 / 1600, True, amp=0.05)
+    Wg = ctx.project(_dev(inputs.taylor_green(ctx.quad_points().cpu().numpy(), mach=0.1)))
+    popts = binding.paper_pmg_opts([2, 1], coarsest_prec=binding.COARSEST_BILU)
+    W1, st = ctx.bdf2_step(Wg, None, 0.05, popts, binding.fgmres_opts(restart=40, rtol=1e-8))
+    err = _rel(W1.cpu().numpy().reshape(Wo.shape), W1o)
+    print("paper preconditioner with BILU: newton %d its %d err %.2e" % (st.newton, st.linear_iters, err), flush=True)
+    assert st.max_rel_res_true <= 1e-8
+    assert err < 1e-10
