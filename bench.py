@@ -240,6 +240,15 @@ def paper_config_steps(args, nsteps):
     return out
 
 
+_T0 = time.perf_counter()
+
+
+def progress(stage):
+    """One line on stderr as each stage of the run ends (the result lines stay
+    on stdout)."""
+    print("# bench: %s done at %.1f s" % (stage, time.perf_counter() - _T0), file=sys.stderr, flush=True)
+
+
 def run(args):
     import torch
 
@@ -259,6 +268,7 @@ def run(args):
     fams = kernel_families(ctx, wl, W0, popts64)
     dom = max(fams, key=lambda k: fams[k]["ms_total"]) if fams else None
     roof = roofline_of(fams, dom, ctx, popts64, args.workload) if dom else None
+    progress("FP64 steps of " + args.workload)
 
     # ---- mixed-precision steps of the same workload ------------------------------------
     fams32 = None
@@ -271,10 +281,12 @@ def run(args):
             "mixed_max_rel_res_true": max(s_.max_rel_res_true for s_ in st32),
             "mixed_vs_fp64_rel": (W32 - W64).norm().item() / W64.norm().item()})
         fams32 = kernel_families(ctx, wl, W0, popts32)
+        progress("mixed steps of " + args.workload)
 
     # ---- J.v throughput -----------------------------------------------------------------
     jv = jvp_rates(ctx, W0, args.jvp_reps)
     ndof, ne, pdeg = ctx.ndof, ctx.ne, ctx.p
+    progress("J.v rates")
     ctx.close()
     del W0, W64
     torch.cuda.empty_cache()
@@ -282,6 +294,7 @@ def run(args):
         jv["fd_32cube"] = large_jvp()
     if not args.no_matrix_based and args.workload == "tgv_p3_16":
         jv["matrix_based"] = matrix_based_jvp(WORKLOADS[args.workload])
+    progress("large and matrix-based J.v")
 
     # ---- the paper's own solver configuration on the same workload ------------------------
     # ESDIRK3 (Sec. 4) with the preconditioner lagged over the step, full
@@ -289,6 +302,7 @@ def run(args):
     # GMRES preconditioned by block ILU(0) in MDF order (Table MGSettings).
     if args.workload == "tgv_p3_16" and not args.no_paper_config:
         steps_out["tgv_p3_16_paper_config"] = paper_config_steps(args, max(1, min(args.steps, args.c3_steps)))
+        progress("ESDIRK3 steps with the paper's preconditioner")
 
     # ---- the curved p = 4 low-Mach workload, FP64 and mixed -----------------------------
     if args.workload == "tgv_p3_16" and not args.no_c3:
@@ -299,22 +313,27 @@ def run(args):
         ctx3.close()
         del W3
         torch.cuda.empty_cache()
+        progress("curved p = 4 steps")
 
     # ---- batching (96 independent cases) and serving (Poisson request stream) ----------
     batch = None
     if not args.no_batch and args.workload == "tgv_p3_16":
         batch = batch_bench(args)
+        progress("batch")
     serving = None
     if not args.no_serving and args.workload == "tgv_p3_16" and args.serve_count > 0:
         from paper_1812_04789_amd import serve
         serving = serve.run(count=args.serve_count, rate=200.0, seed=1812, slots=args.serve_slots)
         # the same stream offered below saturation: latency without queueing
         serving["below_saturation"] = serve.run(count=40, rate=4.0, seed=1813, slots=args.serve_slots)
+        serving["sustainable"] = sustainable_rate(args)
+        progress("serving")
 
     # ---- CPU baseline: the oracle on a bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tgv_p3_16":
         cpu = cpu_baseline()
+        progress("CPU baseline")
 
     # Full detail first (one line), then the compact result line the driver reads.
     detail = {"kernels_fp64": fams, "kernels_mixed": fams32, "jvp": jv, "time_step": steps_out,
@@ -359,6 +378,17 @@ def run(args):
         "jvp_roofline": jroof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
+    if batch is not None:
+        out["batch"] = {"cases": batch["cases"], "total_dof": batch["total_dof"],
+                        "bdf2_step_s": r3(batch["bdf2_step"]["seconds"]),
+                        "bdf2_gdof_s": r3(batch["bdf2_step"]["gdof_s"]),
+                        "fd_jvp_gdof_s": r3(batch["jvp"]["jvp_fd"]["gdof_s"])}
+    if serving is not None:
+        out["serving"] = {"rate_req_s": serving["rate_req_s"], "throughput_req_s": r3(serving["throughput_req_s"]),
+                          "latency_p50_s": r3(serving["latency_s"]["p50"]),
+                          "latency_p99_s": r3(serving["latency_s"]["p99"]),
+                          "aggregate_gdof_s": r3(serving["aggregate_gdof_s"]),
+                          "max_sustained_req_s": serving["sustainable"]["max_sustained_req_s"]}
     print(json.dumps(out), flush=True)
 
 
@@ -475,16 +505,17 @@ def batch_bench(args):
     jv["jvp_fd"]["ms_one_launch_per_case"] = ms_sep
     jv["jvp_fd"]["batching_speedup"] = ms_sep / jv["jvp_fd"]["ms_tuned"]
     out["jvp"] = jv
-    # one BDF2 step of every case, mixed precision, cases concurrent on 8 worker streams
+    # one BDF2 step of every case, mixed precision, cases concurrent on worker streams
     popts = [serve.solver_opts(c["p"], True)[0] for c in wl]
     fopts = binding.fgmres_opts(restart=40, rtol=1e-8)
-    b.bdf2_step(W0, None, 0.05, popts, fopts, workers=8, raise_on_noconv=False)   # warm-up (allocations)
+    nw = args.batch_workers
+    b.bdf2_step(W0, None, 0.05, popts, fopts, workers=nw, raise_on_noconv=False)   # warm-up (allocations)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    W1, st, status = b.bdf2_step(W0, None, 0.05, popts, fopts, workers=8, raise_on_noconv=False)
+    W1, st, status = b.bdf2_step(W0, None, 0.05, popts, fopts, workers=nw, raise_on_noconv=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    out["bdf2_step"] = {"seconds": el, "gdof_s": b.ndof / el / 1e9, "workers": 8, "status": status,
+    out["bdf2_step"] = {"seconds": el, "gdof_s": b.ndof / el / 1e9, "workers": nw, "status": status,
                         "max_rel_res_true": max(x.max_rel_res_true for x in st),
                         "newton_max": max(x.newton for x in st),
                         "linear_iters_mean": float(np.mean([x.linear_iters for x in st])),
@@ -537,6 +568,29 @@ def calibrate_copy():
     del x, y
 
 
+def sustainable_rate(args, rates=(6.0, 10.0, 14.0, 18.0, 22.0, 26.0), count=90):
+    """The same kind of request stream offered at several rates below the
+    200 req/s of the workload: a rate is sustained when the queueing p99 stays
+    below the service p99 (the queue does not grow over the run).  Returns
+    each probe's latency figures and the highest sustained rate."""
+    from paper_1812_04789_amd import serve
+    probes = []
+    best = None
+    for r in rates:
+        out = serve.run(count=count, rate=r, seed=1814, slots=args.serve_slots)
+        ok = out["queue_s"]["p99"] < out["service_s"]["p99"]
+        probes.append({"rate_req_s": r, "throughput_req_s": out["throughput_req_s"],
+                       "latency_p50_s": out["latency_s"]["p50"], "latency_p99_s": out["latency_s"]["p99"],
+                       "queue_p99_s": out["queue_s"]["p99"], "service_p99_s": out["service_s"]["p99"],
+                       "aggregate_gdof_s": out["aggregate_gdof_s"], "sustained": ok})
+        progress("serving probe at %.0f req/s" % r)
+        if ok:
+            best = r
+        else:
+            break
+    return {"requests_per_probe": count, "probes": probes, "max_sustained_req_s": best}
+
+
 def cpu_baseline():
     """The oracle (plain NumPy FP64, as it stands) timed on the host: the
     residual and the FD product of Eq. DG-mf on (a) the whole 4^3 p = 2 Euler
@@ -568,7 +622,7 @@ def cpu_baseline():
         "vortex_p2_4": dict(mesh=omesh.BoxMesh((4, 4, 4), (0, 0, 0), (10, 10, 10)), p=2, mu=0.0, Pr=0.72,
                             ic=lambda x: inputs.isentropic_vortex(x, mach=0.5), reps=5),
         "tgv_p3_16_slab_2x16x16": dict(mesh=omesh.BoxMesh((2, 16, 16), (0, 0, 0), (L / 8, L, L)), p=3,
-                                       mu=1.0 / 1600, Pr=0.71, ic=lambda x: inputs.taylor_green(x, mach=0.1), reps=1),
+                                       mu=1.0 / 1600, Pr=0.71, ic=lambda x: inputs.taylor_green(x, mach=0.1), reps=3),
     }
     res = {}
     for name, c in cases.items():
@@ -615,6 +669,7 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=3, help="timed steps of the curved p=4 workload (at most --steps)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batch-workers", type=int, default=16, help="host threads (and streams) of the batch step")
     ap.add_argument("--serve-count", type=int, default=400)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--jvp-only", action="store_true",
