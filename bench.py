@@ -232,6 +232,13 @@ def paper_config_steps(args, nsteps):
             worst = max(worst, st.max_rel_res_true)
         torch.cuda.synchronize()
         out[tag] = (time.perf_counter() - t0) / nsteps
+        # per-family device time of one more (instrumented) step
+        ctx.timing(True)
+        ctx.esdirk3_step(W0, wl["dt"], popts, fopts)
+        torch.cuda.synchronize()
+        kern = ctx.timing_read()
+        ctx.timing(False)
+        out[tag + "_kernels_ms"] = {k: round(v[0], 3) for k, v in kern.items() if v[1]}
         out[tag + "_fgmres_iters"] = its
         out[tag + "_newton"] = newt
         out[tag + "_max_rel_res_true"] = worst
