@@ -264,6 +264,191 @@ __global__ void __launch_bounds__(128) bilu_apply_kernel(MeshDev m, int nb, cons
     }
 }
 
+// One step of the pipelined apply: steps 0..nx-1 are the forward sweep in
+// elimination order, steps nx..2nx-1 the backward sweep in reverse order.
+// The step's blocks: the couplings of its element k to the line neighbours
+// eliminated before k (forward: L) or after k (backward: U), then, backward,
+// U_kk^-1; src/dst are line-local element indices (e = line nx + i).  ordl
+// and posl are the line's order and positions (line-local, in LDS).
+struct BiluStep {
+    const double* blk[3];
+    int nbk, ncoup;
+    int src[2];
+    int dst;
+};
+
+__device__ __forceinline__ BiluStep bilu_step(const MeshDev& m, const int* ordl, const int* posl,
+                                              const double* __restrict__ d, const double* __restrict__ o, int line,
+                                              int step, int nb) {
+    const int nx = m.nx, base = line * nx;
+    const bool fwd = step < nx;
+    const int i = ordl[fwd ? step : 2 * nx - 1 - step];
+    const int k = base + i;
+    const size_t nn = (size_t)nb * nb;
+    const int j0 = line_nbr(m, k, 0) - base, j1 = line_nbr(m, k, 1) - base;
+    const bool use0 = j0 != i && (fwd ? posl[j0] < posl[i] : posl[j0] > posl[i]);
+    const bool use1 = j1 != i && j1 != j0 && (fwd ? posl[j1] < posl[i] : posl[j1] > posl[i]);
+    const double* c0 = o + ((size_t)k * 2 + 0) * nn;
+    const double* c1 = o + ((size_t)k * 2 + 1) * nn;
+    const double* dk = d + (size_t)k * nn;
+    // the used couplings first (slot order), then, backward, U_kk^-1
+    BiluStep S;
+    S.ncoup = (use0 ? 1 : 0) + (use1 ? 1 : 0);
+    S.nbk = S.ncoup + (fwd ? 0 : 1);
+    S.blk[0] = use0 ? c0 : (use1 ? c1 : dk);
+    S.blk[1] = (use0 && use1) ? c1 : dk;
+    S.blk[2] = dk;
+    S.src[0] = use0 ? j0 : j1;
+    S.src[1] = j1;
+    S.dst = i;
+    return S;
+}
+
+// The same z = (L U)^-1 r with the block size fixed (NB): the line's vector,
+// order and positions are held in LDS, every block product is split over
+// 240 threads (NB rows x six column groups, partial sums added in group
+// order), and the blocks of step s + 1 are written to LDS at the end of step
+// s from registers loaded two steps earlier (two LDS buffers of three blocks,
+// two register sets).  One workgroup per line.
+constexpr int BILU_PIPE_NB = 40;
+constexpr int BILU_PIPE_THREADS = 256;
+constexpr int BILU_PIPE_GROUPS = 6;
+__host__ __device__ constexpr size_t bilu_pipe_lds(int nb, int nx) {
+    return (size_t)(6 * nb * nb + BILU_PIPE_GROUPS * nb + nb + nx * nb) * sizeof(double) + 2 * nx * sizeof(int);
+}
+
+template <int NB, int PER>
+__device__ __forceinline__ void bilu_prefetch(const BiluStep& S, int t, double (&pre)[PER]) {
+    constexpr int NN = NB * NB;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int q = t + BILU_PIPE_THREADS * u;
+        const int b = q / NN;
+        const double* src = (b == 0) ? S.blk[0] : ((b == 1) ? S.blk[1] : S.blk[2]);
+        pre[u] = (q < 3 * NN && b < S.nbk) ? src[q - b * NN] : 0.0;
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(BILU_PIPE_THREADS) bilu_apply_pipe_kernel(
+    MeshDev m, const int* __restrict__ ord, const int* __restrict__ pos, const double* __restrict__ d,
+    const double* __restrict__ o, const double* __restrict__ r, double* __restrict__ z) {
+    constexpr int NN = NB * NB;
+    constexpr int NT = BILU_PIPE_THREADS;
+    constexpr int PER = (3 * NN + NT - 1) / NT;      // prefetched entries per thread and step
+    constexpr int NG = BILU_PIPE_GROUPS;
+    constexpr int CW = (NB + NG - 1) / NG;            // columns per group
+    static_assert(NG * NB <= NT, "one thread per (row, column group)");
+    extern __shared__ double sm[];
+    double* buf0 = sm;
+    double* buf1 = sm + 3 * NN;
+    double* part = sm + 6 * NN;                       // [group][row]
+    double* vb = part + NG * NB;                      // backward: r_k - U x before U_kk^-1
+    const int nx = m.nx, line = blockIdx.x, t = threadIdx.x;
+    double* zl = vb + NB;                             // the line's vector [i][row]
+    int* ordl = reinterpret_cast<int*>(zl + nx * NB);
+    int* posl = ordl + nx;
+    const int row = t % NB, g = t / NB;
+    const int base = line * nx;
+    const double* rl = r + (size_t)base * NB;
+    for (int q = t; q < nx * NB; q += NT) zl[q] = rl[q];
+    for (int q = t; q < nx; q += NT) {
+        ordl[q] = ord[base + q] - base;
+        posl[q] = pos[base + q];
+    }
+    __syncthreads();
+    const int nsteps = 2 * nx;
+    BiluStep S = bilu_step(m, ordl, posl, d, o, line, 0, NB);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b < S.nbk)
+            for (int q = t; q < NN; q += NT) buf0[b * NN + q] = S.blk[b][q];
+    // two register sets: at step s, set A holds step s + 1's blocks (loaded
+    // two steps earlier) and set B step s + 2's; after A is written to LDS it
+    // takes step s + 3's loads, and the sets swap roles
+    BiluStep SA, SB;
+    double preA[PER], preB[PER];
+    if (nsteps > 1) {
+        SA = bilu_step(m, ordl, posl, d, o, line, 1, NB);
+        bilu_prefetch<NB, PER>(SA, t, preA);
+    }
+    if (nsteps > 2) {
+        SB = bilu_step(m, ordl, posl, d, o, line, 2, NB);
+        bilu_prefetch<NB, PER>(SB, t, preB);
+    }
+    __syncthreads();
+    auto body = [&](int step, BiluStep& Sn, double (&pn)[PER]) {
+        const double* cur = (step & 1) ? buf1 : buf0;
+        double* nxt = (step & 1) ? buf0 : buf1;
+        const bool fwd = step < nx;
+        // coupling products of the step, split by column group
+        if (t < NG * NB) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (s < S.ncoup) {
+                    const double* B = cur + s * NN;
+                    const double* x = zl + S.src[s] * NB;
+#pragma unroll
+                    for (int cc = 0; cc < CW; ++cc) {
+                        const int c = g * CW + cc;
+                        if (c < NB) acc = fma(B[c * NB + row], x[c], acc);
+                    }
+                }
+            }
+            part[g * NB + row] = acc;
+        }
+        __syncthreads();
+        if (t < NB) {
+            double y = zl[S.dst * NB + t];
+#pragma unroll
+            for (int gg = 0; gg < NG; ++gg) y -= part[gg * NB + t];
+            if (fwd) zl[S.dst * NB + t] = y;
+            else vb[t] = y;
+        }
+        __syncthreads();
+        if (!fwd) {
+            // z_k = U_kk^-1 (r_k - sum U x)
+            if (t < NG * NB) {
+                const double* X = cur + S.ncoup * NN;
+                double acc = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < CW; ++cc) {
+                    const int c = g * CW + cc;
+                    if (c < NB) acc = fma(X[c * NB + row], vb[c], acc);
+                }
+                part[g * NB + row] = acc;
+            }
+            __syncthreads();
+            if (t < NB) {
+                double y = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < NG; ++gg) y += part[gg * NB + t];
+                zl[S.dst * NB + t] = y;
+            }
+        }
+        if (step + 1 < nsteps) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int q = t + NT * u;
+                if (q < 3 * NN && q / NN < Sn.nbk) nxt[q] = pn[u];
+            }
+            S = Sn;
+            if (step + 3 < nsteps) {
+                Sn = bilu_step(m, ordl, posl, d, o, line, step + 3, NB);
+                bilu_prefetch<NB, PER>(Sn, t, pn);
+            }
+        }
+        __syncthreads();
+    };
+    for (int step = 0; step < nsteps; step += 2) {
+        body(step, SA, preA);
+        if (step + 1 < nsteps) body(step + 1, SB, preB);
+    }
+    double* zo = z + (size_t)base * NB;
+    for (int q = t; q < nx * NB; q += NT) zo[q] = zl[q];
+}
+
 // d <- diag (copy); o[e][s] <- the coupling of e to its line neighbour in
 // slot s from the face blocks off[e][f][c][r] (faces 0 and 1).
 __global__ void bilu_gather_kernel(MeshDev m, int nb, const double* __restrict__ diag, const double* __restrict__ off,
@@ -306,6 +491,15 @@ hipError_t launch_bilu_factor(const DGArgs& a, int nb, const int* ord, const int
 hipError_t launch_bilu_apply(const DGArgs& a, int nb, const int* ord, const int* pos, const double* d,
                              const double* o, const double* r, double* z, hipStream_t s) {
     if (nb > BILU_MAX_N) return hipErrorInvalidValue;
+    const size_t lds = bilu_pipe_lds(nb, a.m.nx);
+    if (nb == BILU_PIPE_NB && lds <= 160 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)bilu_apply_pipe_kernel<BILU_PIPE_NB>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(bilu_apply_pipe_kernel<BILU_PIPE_NB>, dim3(a.m.ne / a.m.nx), dim3(BILU_PIPE_THREADS), lds,
+                           s, a.m, ord, pos, d, o, r, z);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(bilu_apply_kernel, dim3(a.m.ne / a.m.nx), dim3(128), 0, s, a.m, nb, ord, pos, d, o, r, z);
     return hipGetLastError();
 }
