@@ -99,7 +99,11 @@ def run(count=400, rate=200.0, seed=1812, slots=8, hbm_budget=0.0, dt=0.05, requ
         "statuses": sorted(set(status)), "last_error": err or None,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
                       "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
-        "queue_s": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
+        "queue_s": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99)),
+                    # queueing of the first and last third of the arrivals: a growing queue
+                    # (offered rate above what the device serves) shows as last >> first
+                    "first_third_p50": float(np.percentile(queue[:max(1, len(queue) // 3)], 50)),
+                    "last_third_p50": float(np.percentile(queue[-max(1, len(queue) // 3):], 50))},
         "service_s": {"p50": float(np.percentile(serv, 50)), "p99": float(np.percentile(serv, 99))},
         "aggregate_gdof_s": ndof / (t_last - t_first) / 1e9,
         "throughput_req_s": len(reqs) / (t_last - t_first),
