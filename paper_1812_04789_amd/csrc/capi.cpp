@@ -86,7 +86,7 @@ struct Level {
     DBuf<float> f32;      // factors (FP32)
     DBuf<int> piv, pos;
     bool use32 = false;
-    bool inv = false;          // explicit inverse (nb <= INV_MAX_N) applied by GEMV
+    bool inv = false;          // explicit inverse (nb <= INV_POLICY_N) applied by GEMV
     bool inv_done = false;     // inverse already formed during setup (folded level)
     bool fold = false;         // coarsest assembled level stored as K D^-1 (unit diagonal, 6 face blocks)
     DBuf<double> inv64;
