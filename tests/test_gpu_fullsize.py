@@ -2,7 +2,12 @@
 configuration the benchmark times (single-case kernels, 16^3 meshes).
 
 * Taylor-Green NS p = 3 on the straight 16^3 box (1,310,720 DOF): the whole
-  residual against the oracle's (relative 1e-12; the oracle takes ~30 s);
+  residual, exact product and FD product (Eq. DG-mf) against the oracle's
+  (relative 1e-12, 1e-12 and 2e-7; the oracle takes ~20 s per real and ~40 s
+  per complex residual); whole columns of every element's diagonal block
+  (Sec. 6.3) against the exact product of unit vectors on one colour class;
+  the block-Jacobi apply of the fine level (FP64 and FP32 factors) against
+  dense solves with those blocks on sampled elements;
 * low-Mach Taylor-Green NS p = 4 on the curved 16^3 mesh (2,560,000 DOF):
   properties that hold at any size (the oracle needs minutes here):
   free-stream preservation, discrete conservation of the mean modes (to
@@ -52,6 +57,76 @@ def test_residual_full_size_p3():
     err = _rel(ctx.residual(_dev(W)).cpu().numpy().reshape(W.shape), D.residual(W))
     print("16^3 p=3 residual (Taylor-Green) rel err %.3e" % err, flush=True)
     assert err < 1e-9
+    ctx.close()
+
+
+def test_products_full_size_p3():
+    """Exact and FD products of the 16^3 p = 3 NS operator against the
+    oracle's, element-wise as well as in norm."""
+    from oracle import linear as olin
+    ctx = binding.Context(N16, (0, 0, 0), (L, L, L), 3, **GAS)
+    D = odg.Discretization(omesh.BoxMesh(N16, (0, 0, 0), (L, L, L), None), 3, **GAS)
+    W = inputs.random_state(ctx.ne, 3, seed=17)
+    v = inputs.random_vector(ctx.ne, 3, seed=18)
+    a = 30.0
+    Wd, vd = _dev(W), _dev(v)
+    ye = ctx.jvp_exact(Wd, vd, a).cpu().numpy().reshape(W.shape)
+    yo = olin.jvp_exact(D, W, v, a)
+    err = _rel(ye, yo)
+    print("16^3 p=3 exact J.v rel err %.3e" % err, flush=True)
+    assert err < 1e-12
+    assert np.abs(ye - yo).max() < 1e-11 * np.abs(yo).max()
+    RWo = D.residual(W)
+    yf = ctx.jvp(Wd, ctx.residual(Wd), vd, a).cpu().numpy().reshape(W.shape)
+    yfo = olin.jvp_fd(D, W, RWo, v, a)
+    err = _rel(yf, yfo)
+    print("16^3 p=3 FD J.v rel err %.3e (vs exact %.3e)" % (err, _rel(yf, yo)), flush=True)
+    assert err < 2e-7
+    assert np.abs(yf - yfo).max() < 1e-6 * np.abs(yfo).max()
+    ctx.close()
+
+
+def test_blocks_and_block_jacobi_full_size_p3():
+    """Diagonal blocks of the 16^3 p = 3 operator (the kernel the benchmark
+    runs: no single-element axis): column j of every block of one colour of
+    the checkerboard equals the exact product (pinned against the oracle at
+    this size above) of the unit vector e_j placed on every element of that
+    colour, restricted to those elements.  Then the fine-level block-Jacobi
+    apply (one-level pMG: z = D^-1 r, batched PLU and blocked triangular
+    solves, FP64 and FP32 factors) against dense solves with the assembled
+    blocks on sampled elements."""
+    ctx = binding.Context(N16, (0, 0, 0), (L, L, L), 3, **GAS)
+    ne, nv = ctx.ne, ctx.nv
+    nb = 5 * nv
+    W = inputs.random_state(ne, 3, seed=19)
+    a = 3.0 / (2 * 0.05)
+    Wd = _dev(W)
+    B = ctx.assemble_diag(Wd, a).cpu().numpy()                 # [e][col][row]
+    idx = np.arange(ne)
+    colour = ((idx % 16) + (idx // 16) % 16 + idx // 256) % 2
+    for c in (0, 1):
+        sel = np.nonzero(colour == c)[0]
+        for j in (0, 77, nb - 1):
+            v = np.zeros((ne, nb))
+            v[sel, j] = 1.0
+            y = ctx.jvp_exact(Wd, _dev(v), a).cpu().numpy().reshape(ne, nb)
+            ref = y[sel]
+            got = B[sel, j, :]
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print("colour %d column %d: max err %.3e" % (c, j, err), flush=True)
+            assert err < 1e-12
+    rng = np.random.default_rng(20)
+    r = rng.standard_normal((ne, nb))
+    sample = rng.choice(ne, 12, replace=False)
+    for fine, tol in ((binding.DG_FP64, 1e-10), (binding.DG_FP32, 1e-4)):
+        ctx.pmg_setup(Wd, a, binding.pmg_opts([3], prec_fine=fine))
+        z = ctx.pmg_apply(_dev(r)).cpu().numpy().reshape(ne, nb)
+        for e in sample:
+            ref = np.linalg.solve(B[e].T, r[e])
+            err = np.linalg.norm(z[e] - ref) / np.linalg.norm(ref)
+            assert err < tol, (fine, e, err)
+        print("block Jacobi (%s) on %d sampled elements: ok" % ("FP64" if fine == binding.DG_FP64 else "FP32",
+                                                                  len(sample)), flush=True)
     ctx.close()
 
 
