@@ -603,7 +603,7 @@ def calibrate_copy():
     del x, y
 
 
-def sustainable_rate(args, rates=(6.0, 10.0, 14.0, 18.0, 22.0, 26.0, 30.0), seconds=8.0):
+def sustainable_rate(args, rates=(6.0, 10.0, 12.0, 14.0, 18.0, 22.0, 26.0, 30.0), seconds=8.0):
     """The same kind of request stream offered at increasing rates below the
     200 req/s of the workload, each for `seconds` of arrivals (at least 60
     requests): a rate is sustained when the queue does not grow over the run
