@@ -514,12 +514,13 @@ def test_esdirk3_step_p3_paper_config_matches_oracle(mixed, p3_oracle):
 
 
 # ---- block ILU(0) with minimum-discarded-fill order on the coarsest level --------------
-@pytest.mark.parametrize("n", [(4, 2, 2), (3, 2, 2), (2, 3, 2)])
+@pytest.mark.parametrize("n", [(4, 2, 2), (3, 2, 2), (2, 3, 2), (8, 2, 1), (7, 2, 1)])
 def test_vcycle_with_bilu_coarsest_matches_oracle(n):
     """A two-level V-cycle 2 -> 1 whose coarsest GMRES is preconditioned by
     block ILU(0) on the element lines along x in minimum-discarded-fill order
-    (Sec. 6.3, Table MGSettings) against the oracle's (lines of four with
-    discarded fill, of three with the wrap coupling kept, of two): 1e-5.  A
+    (Sec. 6.3, Table MGSettings) against the oracle's (lines of four, eight
+    and seven with discarded fill, of three with the wrap coupling kept, of
+    two): 1e-5.  A
     small shift and three coarsest steps keep the coarse solve partial, so
     the result depends on the preconditioner (block Jacobi there differs by
     far more)."""
