@@ -137,17 +137,19 @@ def test_bdf2_step_pmg_matches_oracle(fp32, tgv_oracle):
     assert _rel(W1.cpu().numpy().reshape(Wo.shape), W1o) < 1e-10
 
 
-@pytest.mark.parametrize("cmf", [1, 2])
-def test_vcycle_graph_replays_match_eager(cmf):
+@pytest.mark.parametrize("cmf,cprec", [(1, 0), (2, 0), (2, 1)])
+def test_vcycle_graph_replays_match_eager(cmf, cprec):
     """pmg_apply replays a captured HIP graph; every replay, with other eager
     work and synchronisations in between, equals the eager V-cycle bitwise
     (all kernels, reductions included, are deterministic).  cmf = 2: the
-    assembled coarsest level runs on the folded operator K D^-1."""
-    ctx, _ = _case((2, 3, 2), 2, 0.02, True)
+    assembled coarsest level runs on the folded operator K D^-1, or (cprec =
+    1) on the 7-block operator with the block ILU(0) preconditioner, on lines
+    of four elements."""
+    ctx, _ = _case((4, 3, 2), 2, 0.02, True)
     W = _dev(inputs.random_state(ctx.ne, 2, seed=51))
     r1 = _dev(inputs.random_vector(ctx.ne, 2, seed=52))
     r2 = _dev(inputs.random_vector(ctx.ne, 2, seed=53))
-    ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12, coarse_matrix_free=cmf))
+    ctx.pmg_setup(W, 20.0, binding.pmg_opts([2, 1], coarsest_iters=12, coarse_matrix_free=cmf, coarsest_prec=cprec))
     ctx.use_graphs(False)
     z1 = ctx.pmg_apply(r1).clone()
     z2 = ctx.pmg_apply(r2).clone()
