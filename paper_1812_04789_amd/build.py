@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdg_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["dg_kernels.hip", "la_kernels.hip", "lu_kernels.hip", "bj_apply.hip", "bilu.hip", "tables.cpp", "capi.cpp",
-           "batch.cpp", "server.cpp"]
+SOURCES = ["dg_kernels.hip", "la_kernels.hip", "lu_kernels.hip", "bj_apply.hip", "bilu.hip", "bilu_order.cpp",
+           "tables.cpp", "capi.cpp", "batch.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
