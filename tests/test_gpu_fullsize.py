@@ -9,7 +9,8 @@ configuration the benchmark times (single-case kernels, 16^3 meshes).
   the block-Jacobi apply of the fine level (FP64 and FP32 factors) against
   dense solves with those blocks on sampled elements;
 * low-Mach Taylor-Green NS p = 4 on the curved 16^3 mesh (2,560,000 DOF):
-  properties that hold at any size (the oracle needs minutes here):
+  the residual on a random state against the oracle's (1e-12; about two
+  minutes of oracle time), and properties that hold at any size:
   free-stream preservation, discrete conservation of the mean modes (to
   rounding of the face fluxes), the exact product linear in v, the FD
   product of Eq. DG-mf within its truncation error of the exact product, and
@@ -128,6 +129,24 @@ def test_blocks_and_block_jacobi_full_size_p3():
         print("block Jacobi (%s) on %d sampled elements: ok" % ("FP64" if fine == binding.DG_FP64 else "FP32",
                                                                   len(sample)), flush=True)
     ctx.close()
+
+
+def test_residual_full_size_p4_curved():
+    """The NS residual on the curved 16^3 p = 4 mesh of the low-Mach workload
+    (2,560,000 DOF, the kernel the benchmark's curved workload runs) against
+    the oracle's on a seeded random state: 1e-12 relative, element-wise too
+    (the oracle takes about two minutes here)."""
+    vtx = inputs.box_vertices(N16, (0, 0, 0), (L, L, L), amp=0.05)
+    ctx = binding.Context(N16, (0, 0, 0), (L, L, L), 4, vertices=vtx, **GAS)
+    D = odg.Discretization(omesh.BoxMesh(N16, (0, 0, 0), (L, L, L), vtx), 4, **GAS)
+    W = inputs.random_state(ctx.ne, 4, seed=26)
+    R = ctx.residual(_dev(W)).cpu().numpy().reshape(W.shape)
+    ctx.close()
+    Ro = D.residual(W)
+    err = _rel(R, Ro)
+    print("curved 16^3 p=4 residual (random state) rel err %.3e" % err, flush=True)
+    assert err < 1e-12
+    assert np.abs(R - Ro).max() < 1e-11 * np.abs(Ro).max()
 
 
 def test_properties_full_size_tgv_p4_curved():
