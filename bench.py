@@ -545,7 +545,7 @@ def kernel_name(family, p, popts):
     return {"residual": "dg_kernel<P,NS,CURVED,0>", "jvp_fd": "dg_kernel<P,NS,CURVED,1>",
             "jvp_exact": "dg_kernel<P,NS,CURVED,2>", "diag_blocks": "diag_kernel", "lu": "lu_blocked_kernel<double>",
             "bsr": "bsr_rows_kernel<double,double,UNIT,DOTS>", "bj_coarse": "inv_gemv_kernel<double>",
-            "arnoldi": "gs_update_kernel + gs_normalise_kernel (+ gs_dots_kernel)"}.get(family, family)
+            "arnoldi": "gs_update_kernel + gs_update_normalise_kernel (+ gs_dots_kernel)"}.get(family, family)
 
 
 def measured_traffic(kname, workload):

@@ -58,7 +58,7 @@ struct DBuf {
 struct Krylov {
     int m = 0;
     size_t N = 0;
-    DBuf<double> V, Z, H, cs, sn, g, y, h2, sc;
+    DBuf<double> V, Z, H, cs, sn, g, y, sc;
     void ensure(int m_, size_t N_) {
         m = m_;
         N = N_;
@@ -69,12 +69,11 @@ struct Krylov {
         sn.ensure(m);
         g.ensure(m + 1);
         y.ensure(m);
-        h2.ensure(m + 1);
         sc.ensure(8);
     }
     void release() {
         V.release(); Z.release(); H.release(); cs.release(); sn.release(); g.release(); y.release();
-        h2.release(); sc.release();
+        sc.release();
     }
 };
 
@@ -328,8 +327,8 @@ void smooth(dg_ctx* ctx, int l, double* x, const double* b, int nu, bool x_zero)
 
 // Arnoldi step j with classical Gram-Schmidt applied twice; w is in V[j+1].
 void arnoldi_orth(dg_ctx* ctx, Krylov& K, int j, size_t n) {
-    timed(ctx, DG_K_ARNOLDI, 32.0 * (j + 1) * (double)n, 8.0 * (j + 1) * (double)n, [&] {
-        return launch_arnoldi_cgs2(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p, K.sc.p + 1,
+    timed(ctx, DG_K_ARNOLDI, 24.0 * (j + 1) * (double)n + 32.0 * (double)n, 6.0 * (j + 1) * (double)n, [&] {
+        return launch_arnoldi_cgs2(K.V.p, n, j, K.H.p, K.m + 1, K.cs.p, K.sn.p, K.g.p, K.sc.p + 1,
                                    K.sc.p + 2, ctx->partial.p, ctx->s);
     });
 }
@@ -380,8 +379,8 @@ void coarse_gmres(dg_ctx* ctx, int l, const double* b, double* x, int iters) {
                 return launch_bsr_unit_dots<unsigned short>(ctx->a, L.op16.p, x, y, L.nb, K.V.p, j + 1,
                                                             ctx->partial.p, &np, ctx->s);
             });
-            timed(ctx, DG_K_ARNOLDI, 24.0 * (j + 1) * (double)n, 6.0 * (j + 1) * (double)n, [&] {
-                return launch_arnoldi_cgs2_after_dots(K.V.p, n, j, K.H.p, K.m + 1, K.h2.p, K.cs.p, K.sn.p, K.g.p,
+            timed(ctx, DG_K_ARNOLDI, 16.0 * (j + 1) * (double)n + 32.0 * (double)n, 4.0 * (j + 1) * (double)n, [&] {
+                return launch_arnoldi_cgs2_after_dots(K.V.p, n, j, K.H.p, K.m + 1, K.cs.p, K.sn.p, K.g.p,
                                                       K.sc.p + 1, K.sc.p + 2, ctx->partial.p, np, ctx->s);
             });
         }
@@ -986,7 +985,7 @@ template <class T>
 double bytes_of(const DBuf<T>& b) { return (double)b.n * sizeof(T); }
 double krylov_bytes(const Krylov& K) {
     return bytes_of(K.V) + bytes_of(K.Z) + bytes_of(K.H) + bytes_of(K.cs) + bytes_of(K.sn) + bytes_of(K.g) +
-           bytes_of(K.y) + bytes_of(K.h2) + bytes_of(K.sc);
+           bytes_of(K.y) + bytes_of(K.sc);
 }
 }  // namespace
 
@@ -1015,7 +1014,7 @@ extern "C" double dg_footprint_bytes(const dg_mesh_desc* mesh, int p, const pmg_
     const double ne = (double)mesh->nx * mesh->ny * mesh->nz;
     const double nv = (p + 1.0) * (p + 1) * (p + 1), nb = 5 * nv, N = ne * nb;
     // Krylov workspace of restart m on n entries (basis V, directions Z, Hessenberg and rotations)
-    auto krylov = [](double m, double n) { return (2 * m + 1) * n * 8 + ((m + 1) * m + 5 * m + 2 + 8) * 8; };
+    auto krylov = [](double m, double n) { return (2 * m + 1) * n * 8 + ((m + 1) * m + 4 * m + 1 + 8) * 8; };
     double b = 24 * ne * 8 + (double)RED_BLOCKS * 256 * 8 + S_COUNT * 8 + 4 * 4 + 3 * N * 8;   // create
     b += 2 * N * 8 + ne * nb * fine_block_ld((int)nb) * 8 + (double)nbr_trace_size(p, (int)ne) * 8;  // W0, RW0, blocks, traces
     double tmp = 0.0;

@@ -139,15 +139,17 @@ hipError_t launch_prolong_add(int ne, int nvf, int nvc, const double* coarse, do
                               hipStream_t s);
 hipError_t launch_count_nonfinite(size_t n, const double* x, int* flag, hipStream_t s);
 // One Arnoldi step j (basis V[0..j], new vector in V[j+1]): classical
-// Gram-Schmidt twice, H column j, norm, Givens rotation j, normalisation;
-// est = |g_{j+1}|.  j + 1 <= 64.  partial: 3 * 64 * RED_BLOCKS doubles.
-hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
-                               double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s);
+// Gram-Schmidt twice (the norm after the second pass from the first-pass norm
+// and the second-pass coefficients), H column j, Givens rotation j,
+// normalisation; est = |g_{j+1}|.  j + 1 <= 64.  partial: RED_BLOCKS * 256
+// doubles (the context's reduction buffer).
+hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* cs, double* sn,
+                               double* g, double* nrm, double* est, double* partial, hipStream_t s);
 // The same step when the first-pass partial dots V_i . w (i <= j) are already
 // in partial[i * np_a + b], b < np_a <= RED_BLOCKS (launch_bsr_unit_dots).
-hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* h2,
-                                          double* cs, double* sn, double* g, double* nrm, double* est,
-                                          double* partial, int np_a, hipStream_t s);
+hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* cs,
+                                          double* sn, double* g, double* nrm, double* est, double* partial, int np_a,
+                                          hipStream_t s);
 
 // ---- dense block kernels (lu_kernels.hip) ------------------------------------
 template <class TF>

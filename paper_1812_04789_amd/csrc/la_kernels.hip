@@ -275,24 +275,28 @@ hipError_t launch_init_g(double* g, int len, const double* beta2, hipStream_t s)
 }
 
 // ---- fused classical Gram-Schmidt (applied twice) for one Arnoldi step -----------------------
-// Step j, w = V[j+1], basis V[0..j]; four launches, no inter-block
+// Step j, w = V[j+1], basis V[0..j]; three launches, no inter-block
 // synchronisation inside a launch:
 //   K1  pa = per-block partials of V_i . w                     (i <= j)
 //   K2  h  = sum of pa (every block; block 0 stores H column j);
-//       w -= sum_i h_i V_i ; pb = partials of V_i . w          (second pass)
-//   K3  h2 = sum of pb (every block; block 0 stores h2);
-//       w -= sum_i h2_i V_i ; pc = partials of w . w
-//   K4  nrm2 = sum of pc (every block); w /= ||w||; block 0: h += h2,
-//       H[j+1,j] = ||w||, Givens rotation j, est = |g_{j+1}|
+//       w -= sum_i h_i V_i ; pb = partials of V_i . w (second pass, i <= j)
+//       and of w . w (column j + 1)
+//   K3  h2, ||w||^2 = sums of pb (every block); the norm after the second
+//       update by Pythagoras, ||w - V h2||^2 = ||w||^2 - ||h2||^2 (exact for
+//       orthonormal V; after the first pass h2 is at rounding level against
+//       w, so the difference keeps full relative precision), clamped at 0;
+//       w <- (w - sum_i h2_i V_i) / norm; block 0: H column j += h2,
+//       H[j+1,j] = norm, Givens rotation j, est = |g_{j+1}|
 // Every block sums the previous launch's partials in the same fixed order,
 // so all blocks hold bitwise the same coefficients and the result depends
-// only on the data.  pa, pb, pc are disjoint (a launch reads one set while
-// writing the next).
+// only on the data.  pa and pb are disjoint (K2 reads one set while writing
+// the other).
 constexpr int GS_CH = 16;
 constexpr int GS_BLOCKS = 256;
-static_assert(3 * GS_MAXK * RED_BLOCKS <= RED_BLOCKS * 256, "the partial buffer holds three sets of partials");
+static_assert(2 * GS_MAXK * RED_BLOCKS + (GS_MAXK + 1) * GS_BLOCKS <= RED_BLOCKS * 256,
+              "the partial buffer holds the first-pass set and the second-pass set with its norm column");
 
-// out[c] = sum_{b < nparts} part[c * nparts + b] for c < k <= 64, into LDS
+// out[c] = sum_{b < nparts} part[c * nparts + b] for c < k <= 65, into LDS
 // (all threads see it after the call).  A group of g threads (a power of two,
 // g k <= blockDim.x, g <= 64) takes output c: thread i of the group sums
 // b = i, i + g, ... into eight accumulators (b = i + g (8 m + u) into u, the
@@ -347,29 +351,18 @@ __global__ void __launch_bounds__(RED_THREADS)
     gs_block_dots(V, n, k, w, pa, sh);
 }
 
-// K2 / K3: coefficients from the previous partials, w -= sum_i c_i V_i, then
-// second-pass dots (mode 0, into pout) or the squared norm (mode 1).
+// K2: coefficients from the first-pass partials, w -= sum_i c_i V_i, then the
+// second-pass dots (columns 0..k-1 of pout) and ||w||^2 (column k).
 __global__ void __launch_bounds__(RED_THREADS)
     gs_update_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ pin, int np_in,
-                     double* __restrict__ cout, double* __restrict__ w, double* __restrict__ pout, int mode) {
+                     double* __restrict__ cout, double* __restrict__ w, double* __restrict__ pout) {
     __shared__ double sh[RED_THREADS];
     __shared__ double hs[GS_MAXK];
     sum_parts(pin, np_in, k, hs);
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < k; i += blockDim.x) cout[i] = hs[i];
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    if (mode == 1) {
-        double nrm = 0.0;
-        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-            double wi = w[i];
-            for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
-            w[i] = wi;
-            nrm = fma(wi, wi, nrm);
-        }
-        const double sm = block_sum(nrm, sh);
-        if (threadIdx.x == 0) pout[blockIdx.x] = sm;
-        return;
-    }
+    double nrm = 0.0;
     if (k <= 2 * GS_CH) {
         // one pass: the basis entries of a row stay in registers for the
         // update and the dots (the same per-thread sums as the two passes)
@@ -385,6 +378,7 @@ __global__ void __launch_bounds__(RED_THREADS)
             for (int c = 0; c < 2 * GS_CH; ++c)
                 if (c < k) wi -= hs[c] * v[c];
             w[i] = wi;
+            nrm = fma(wi, wi, nrm);
 #pragma unroll
             for (int c = 0; c < GS_CH; ++c) {
                 if (c < k) a0[c] = fma(v[c], wi, a0[c]);
@@ -393,33 +387,45 @@ __global__ void __launch_bounds__(RED_THREADS)
         }
         block_sum_cols<GS_CH>(a0, min(GS_CH, k), sh, pout + blockIdx.x, gridDim.x);
         if (k > GS_CH) block_sum_cols<GS_CH>(a1, k - GS_CH, sh, pout + (size_t)GS_CH * gridDim.x + blockIdx.x, gridDim.x);
-        return;
+    } else {
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            double wi = w[i];
+            for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
+            w[i] = wi;
+            nrm = fma(wi, wi, nrm);
+        }
+        gs_block_dots(V, n, k, w, pout, sh);
     }
+    const double sm = block_sum(nrm, sh);
+    if (threadIdx.x == 0) pout[(size_t)k * gridDim.x + blockIdx.x] = sm;
+}
+
+// K3: second update and normalisation from the second-pass partials; block 0
+// finishes H column j (first-pass coefficients already there) and the Givens
+// rotation.
+__global__ void __launch_bounds__(RED_THREADS)
+    gs_update_normalise_kernel(const double* __restrict__ V, size_t n, int k, const double* __restrict__ pin,
+                               int np_in, double* __restrict__ w, double* H, int ldh, double* cs, double* sn,
+                               double* g, double* nrm_out, double* est) {
+    __shared__ double hs[GS_MAXK + 1];
+    sum_parts(pin, np_in, k + 1, hs);
+    double h22 = 0.0;
+    for (int c = 0; c < k; ++c) h22 = fma(hs[c], hs[c], h22);
+    const double nr2 = hs[k] - h22;
+    const double nr = (nr2 > 0.0) ? sqrt(nr2) : 0.0;
+    const double a = (nr != 0.0) ? 1.0 / nr : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wi = w[i];
         for (int c = 0; c < k; ++c) wi -= hs[c] * V[(size_t)c * n + i];
-        w[i] = wi;
+        w[i] = a * wi;
     }
-    gs_block_dots(V, n, k, w, pout, sh);
-}
-
-// K4: ||w|| from the partials, w /= ||w||; block 0 finishes H column j and
-// the Givens rotation.
-__global__ void __launch_bounds__(RED_THREADS)
-    gs_normalise_kernel(size_t n, double* __restrict__ w, const double* __restrict__ pc, double* H, int ldh, int j,
-                        const double* __restrict__ h2, double* cs, double* sn, double* g, double* nrm_out,
-                        double* est) {
-    __shared__ double s_n2;
-    sum_parts(pc, gridDim.x, 1, &s_n2);
-    const double nr = sqrt(s_n2);
-    const double a = (nr != 0.0) ? 1.0 / nr : 0.0;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) w[i] = a * w[i];
     if (blockIdx.x != 0) return;
+    const int j = k - 1;
     __shared__ double sh_h[GS_MAXK + 1], sh_c[GS_MAXK], sh_s[GS_MAXK];
     double* h = H + (size_t)j * ldh;
     for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        sh_h[i] = h[i] + h2[i];
+        sh_h[i] = h[i] + hs[i];
         sh_c[i] = cs[i];
         sh_s[i] = sn[i];
     }
@@ -446,39 +452,36 @@ __global__ void __launch_bounds__(RED_THREADS)
     est[0] = fabs(g[j + 1]);
 }
 
-static hipError_t arnoldi_tail(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
-                               double* sn, double* g, double* nrm, double* est, double* partial, int np_a,
-                               hipStream_t s) {
+static hipError_t arnoldi_tail(const double* V, size_t n, int j, double* H, int ldh, double* cs, double* sn,
+                               double* g, double* nrm, double* est, double* partial, int np_a, hipStream_t s) {
     const int k = j + 1;
     const int nbk = red_blocks(n) < GS_BLOCKS ? red_blocks(n) : GS_BLOCKS;
     double* w = const_cast<double*>(V) + (size_t)k * n;
     double* hcol = H + (size_t)j * ldh;
     double* pa = partial;
     double* pb = partial + (size_t)GS_MAXK * RED_BLOCKS;
-    double* pc = partial + (size_t)2 * GS_MAXK * RED_BLOCKS;
-    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pa, np_a, hcol, w, pb, 0);
-    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pb, nbk, h2, w, pc, 1);
-    hipLaunchKernelGGL(gs_normalise_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, n, w, pc, H, ldh, j, h2, cs, sn, g,
-                       nrm, est);
+    hipLaunchKernelGGL(gs_update_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pa, np_a, hcol, w, pb);
+    hipLaunchKernelGGL(gs_update_normalise_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, pb, nbk, w, H, ldh,
+                       cs, sn, g, nrm, est);
     return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* h2, double* cs,
-                               double* sn, double* g, double* nrm, double* est, double* partial, hipStream_t s) {
+hipError_t launch_arnoldi_cgs2(const double* V, size_t n, int j, double* H, int ldh, double* cs, double* sn,
+                               double* g, double* nrm, double* est, double* partial, hipStream_t s) {
     const int k = j + 1;
     if (k > GS_MAXK) return hipErrorInvalidValue;
     // at most one block per CU: every block re-reads all partials of a set
     const int nbk = red_blocks(n) < GS_BLOCKS ? red_blocks(n) : GS_BLOCKS;
     double* w = const_cast<double*>(V) + (size_t)k * n;
     hipLaunchKernelGGL(gs_dots_kernel, dim3(nbk), dim3(RED_THREADS), 0, s, V, n, k, w, partial);
-    return arnoldi_tail(V, n, j, H, ldh, h2, cs, sn, g, nrm, est, partial, nbk, s);
+    return arnoldi_tail(V, n, j, H, ldh, cs, sn, g, nrm, est, partial, nbk, s);
 }
 
-hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* h2,
-                                          double* cs, double* sn, double* g, double* nrm, double* est,
-                                          double* partial, int np_a, hipStream_t s) {
+hipError_t launch_arnoldi_cgs2_after_dots(const double* V, size_t n, int j, double* H, int ldh, double* cs,
+                                          double* sn, double* g, double* nrm, double* est, double* partial, int np_a,
+                                          hipStream_t s) {
     if (j + 1 > GS_MAXK || np_a < 1 || np_a > RED_BLOCKS) return hipErrorInvalidValue;
-    return arnoldi_tail(V, n, j, H, ldh, h2, cs, sn, g, nrm, est, partial, np_a, s);
+    return arnoldi_tail(V, n, j, H, ldh, cs, sn, g, nrm, est, partial, np_a, s);
 }
 
 // ---- per-case FD steps of a batch ------------------------------------------------------------
