@@ -228,11 +228,8 @@ void dot(dg_ctx* ctx, const double* x, const double* y, size_t n, double* out) {
 // y = shift M v + (R(W + h v) - RW)/h.  nw2: device ||W||^2 (computed if null).
 void jvp_fd(dg_ctx* ctx, const double* W, const double* RW, const double* v, double shift, double* y,
             const double* nw2) {
-    if (!nw2) {
-        dot(ctx, W, W, ctx->N, sc(ctx, S_NW2));
-        nw2 = sc(ctx, S_NW2);
-    }
-    CK(launch_fd_step_of(v, ctx->N, nw2, 1e-7, ctx->partial.p, sc(ctx, S_NV2), sc(ctx, S_H), ctx->s));
+    CK(launch_fd_step(v, nw2 ? nullptr : W, ctx->N, nw2, nw2 ? nullptr : sc(ctx, S_NW2), 1e-7, ctx->partial.p,
+                      sc(ctx, S_NV2), sc(ctx, S_H), ctx->s));
     timed(ctx, DG_K_JVP_FD, 32.0 * (double)ctx->N, 0.0, [&] { return launch_jvp_fd(ctx->a, W, RW, v, sc(ctx, S_H), shift, y, ctx->s); });
 }
 

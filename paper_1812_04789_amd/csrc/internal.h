@@ -120,11 +120,12 @@ constexpr int RED_THREADS = 256;
 hipError_t launch_multi_dot(const double* X, size_t ldx, int nx, const double* y, size_t n, double* partial,
                             double* out, hipStream_t s);
 hipError_t launch_dot(const double* x, const double* y, size_t n, double* partial, double* out, hipStream_t s);
-// h = eps sqrt(1 + sqrt(nw2)) / sqrt(nv2), 0 if nv2 == 0
-hipError_t launch_fd_step(const double* nw2, const double* nv2, double eps, double* h, hipStream_t s);
-// nv2 = ||v||^2 (the launch_dot reduction) and h as above, in two launches.
-hipError_t launch_fd_step_of(const double* v, size_t n, const double* nw2, double eps, double* partial, double* nv2,
-                             double* h, hipStream_t s);
+// nv2 = ||v||^2 and h = eps sqrt(1 + ||W||) / ||v|| (0 if v == 0) in two
+// launches, bitwise equal to the launch_dot reductions.  ||W||^2 from nw2_in
+// (W null), or computed from W in the same pass into nw2_out (nw2_in null).
+// partial: the context's reduction buffer.
+hipError_t launch_fd_step(const double* v, const double* W, size_t n, const double* nw2_in, double* nw2_out,
+                          double eps, double* partial, double* nv2, double* h, hipStream_t s);
 hipError_t launch_axpby(size_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s);
 // y += sum_k c[k] * X_k   (c on device), or y -= when sign < 0
 hipError_t launch_multi_axpy(size_t n, int k, const double* c, int sign, const double* X, size_t ldx, double* y,

@@ -68,35 +68,55 @@ hipError_t launch_dot(const double* x, const double* y, size_t n, double* partia
     return launch_multi_dot(x, n, 1, y, n, partial, out, s);
 }
 
-// ||v||^2 from the first-stage partials (the same second stage as sum_stage2),
-// then the FD step h = eps sqrt(1 + ||W||) / ||v|| (0 for v = 0): one block.
-__global__ void __launch_bounds__(RED_THREADS) fd_step_stage2(const double* __restrict__ partial, int nparts,
-                                                              const double* __restrict__ nw2, double eps,
-                                                              double* __restrict__ nv2, double* __restrict__ h) {
+// The FD step of Eq. DG-mf in two launches.  Stage 1: each block's partial
+// of ||v||^2 (column 0) and, when W is given (the caller has no norm of W), of
+// ||W||^2 (column 1), over the grid and per-thread order of multi_dot_stage1.
+// Stage 2 (one block): the sums in the order of sum_stage2, then ||v||^2,
+// ||W||^2 and h = eps sqrt(1 + ||W||) / ||v|| (0 for v = 0).  Bitwise the
+// results of the separate launch_dot reductions.
+__global__ void __launch_bounds__(RED_THREADS)
+    fd_norms_stage1(const double* __restrict__ v, const double* __restrict__ W, size_t n,
+                    double* __restrict__ partial) {
     __shared__ double sh[RED_THREADS];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
-    const double s2 = block_sum(acc, sh);
+    const bool withw = (W != nullptr);
+    double acc[2] = {0.0, 0.0};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double vi = v[i];
+        acc[0] = fma(vi, vi, acc[0]);
+        if (withw) {
+            const double wi = W[i];
+            acc[1] = fma(wi, wi, acc[1]);
+        }
+    }
+    block_sum_cols<2>(acc, withw ? 2 : 1, sh, partial + blockIdx.x, gridDim.x);
+}
+__global__ void __launch_bounds__(RED_THREADS)
+    fd_step_stage2(const double* __restrict__ partial, int nparts, int withw, const double* __restrict__ nw2_in,
+                   double* __restrict__ nw2_out, double eps, double* __restrict__ nv2, double* __restrict__ h) {
+    __shared__ double sh[RED_THREADS];
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a0 += partial[i];
+        if (withw) a1 += partial[nparts + i];
+    }
+    const double s2 = block_sum(a0, sh);
+    const double sw = withw ? block_sum(a1, sh) : 0.0;
     if (threadIdx.x == 0) {
         nv2[0] = s2;
+        if (withw) nw2_out[0] = sw;
+        const double w2 = withw ? sw : nw2_in[0];
         const double nv = sqrt(s2);
-        h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2[0])) / nv : 0.0;
+        h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(w2)) / nv : 0.0;
     }
 }
-hipError_t launch_fd_step_of(const double* v, size_t n, const double* nw2, double eps, double* partial, double* nv2,
-                             double* h, hipStream_t s) {
+hipError_t launch_fd_step(const double* v, const double* W, size_t n, const double* nw2_in, double* nw2_out,
+                          double eps, double* partial, double* nv2, double* h, hipStream_t s) {
+    if ((W == nullptr) == (nw2_in == nullptr) || (W && !nw2_out)) return hipErrorInvalidValue;
     const int nbk = red_blocks(n);
-    hipLaunchKernelGGL(multi_dot_stage1, dim3(nbk), dim3(RED_THREADS), 0, s, v, n, 0, 1, v, n, partial);
-    hipLaunchKernelGGL(fd_step_stage2, dim3(1), dim3(RED_THREADS), 0, s, partial, nbk, nw2, eps, nv2, h);
-    return hipGetLastError();
-}
-
-__global__ void fd_step_kernel(const double* nw2, const double* nv2, double eps, double* h) {
-    const double nv = sqrt(nv2[0]);
-    h[0] = (nv > 0.0) ? eps * sqrt(1.0 + sqrt(nw2[0])) / nv : 0.0;
-}
-hipError_t launch_fd_step(const double* nw2, const double* nv2, double eps, double* h, hipStream_t s) {
-    hipLaunchKernelGGL(fd_step_kernel, dim3(1), dim3(1), 0, s, nw2, nv2, eps, h);
+    hipLaunchKernelGGL(fd_norms_stage1, dim3(nbk), dim3(RED_THREADS), 0, s, v, W, n, partial);
+    hipLaunchKernelGGL(fd_step_stage2, dim3(1), dim3(RED_THREADS), 0, s, partial, nbk, W ? 1 : 0, nw2_in, nw2_out,
+                       eps, nv2, h);
     return hipGetLastError();
 }
 
