@@ -2044,6 +2044,327 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
     }
 }
 
+// Diagonal blocks from Jacobian slices (no face couples the element to
+// itself).  Column (beta, j) of K_e is the derivative of the element
+// residual in the direction of basis function j in variable beta.  That
+// residual sees W_e[beta] only through u_beta and its reference gradient at
+// the Gauss points and through the own trace's value and reference gradient
+// at the face points, and it is linear in each of these directions.  One
+// workgroup per (element slot group, beta) therefore takes, once, with dual
+// numbers: the derivatives of the volume flux term (15 outputs) with
+// respect to u_beta and d u_beta / d xi_m at every Gauss point, and those of
+// the face integrand (20 outputs) with respect to the own trace value and,
+// for the averaged viscous flux (outputs 0..4, the only ones the gradient
+// enters), its reference gradient at every face point: the slices.  Each
+// column j is then these slices contracted with basis function j's values
+// and reference gradients, spread onto the Gauss lines and tested exactly
+// as in the per-column kernel.  Four dual evaluations per point and beta
+// instead of one per column.
+template <int P>
+struct SzS {
+    static constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NFP = 6 * NF;
+    static constexpr int OFF_U = 20 * NQ;        // Gauss values (5NQ); then the first test sweep
+    static constexpr int OFF_G = 25 * NQ;        // reference gradients (15NQ); then the second test sweep and H
+    static constexpr int OFF_FS = 40 * NQ;       // face slices, 35 per face point
+    static constexpr int TOT = OFF_FS + 35 * NFP;
+};
+template <int P> struct LaunchS { static constexpr int EPB = (P == 1) ? 4 : ((P == 2) ? 2 : 1); };
+
+template <int P, bool NS, bool CURVED>
+__global__ void __launch_bounds__((LaunchS<P>::EPB * SzS<P>::NQ))
+    diag_slices_kernel(MeshDev m, Gas gas, const double* __restrict__ W, const double* __restrict__ nbrtr,
+                       double shift, double* __restrict__ out, int ld) {
+    using S_ = SzS<P>;
+    constexpr int N = S_::N, NQ = S_::NQ, NF = S_::NF, NFP = S_::NFP, NB = 5 * NQ;
+    constexpr int EPB = LaunchS<P>::EPB;
+    constexpr int NDIR = NS ? 4 : 1;         // u_beta, then d u_beta / d xi_m (viscous terms only)
+    extern __shared__ double dsm[];
+    __shared__ double svtx[EPB][24];
+    __shared__ short sinv[NQ];              // tensor index of hierarchical mode
+    const Tab& tb = c_tab[P];
+    const short* perm = c_perm + perm_offset(P);
+    const int es = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    const int e = blockIdx.x * EPB + es;
+    const bool active = e < m.ne;
+    const int beta = blockIdx.y;
+    double* S = dsm + (size_t)es * S_::TOT;
+    double* FS = S + S_::OFF_FS;
+    const int ii[3] = {q / NF, (q / N) % N, q % N};
+    if (threadIdx.x < NQ) sinv[perm[threadIdx.x]] = (short)threadIdx.x;
+    if (active) {
+        const size_t base = (size_t)e * NB;
+        const int pm = perm[q];
+        for (int a = 0; a < 5; ++a) S[a * NQ + q] = W[base + a * NQ + pm];
+        if constexpr (CURVED)
+            for (int k = q; k < 24; k += NQ) svtx[es][k] = m.vtx[(size_t)e * 24 + k];
+    }
+    __syncthreads();
+    double* X1 = S + 5 * NQ;
+    double* X2 = S + 10 * NQ;
+    double* su = S + S_::OFF_U;
+    double* sg = S + S_::OFF_G;
+    if (active) sweep<N, 5, false>(tb.V, S, X1, 0, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X1, X2, 1, ii, q);
+    __syncthreads();
+    if (active) sweep<N, 5, false>(tb.V, X2, su, 2, ii, q);
+    __syncthreads();
+    // ---- reference gradients at the Gauss points (LDS, for the own traces)
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc = fma(tb.D[ii[k]][j], su[a * NQ + tix_dir<N>(k, j, ii)], acc);
+                sg[(a * 3 + k) * NQ + q] = acc;
+            }
+    }
+    __syncthreads();
+    // ---- face slices (LDS): per face point fs[0..19] (value direction),
+    // fs[20 + 5 (m - 1) + o] (reference-gradient direction m, outputs o < 5)
+    for (int r = 0; r * NQ < NFP; ++r) {
+        const int fp = r * NQ + q;
+        if (active && fp < NFP) {
+            const int f = fp / NF, fq = fp % NF;
+            const int d = f >> 1, s = f & 1;
+            const int qt1 = fq / N, qt2 = fq % N;
+            const int sd = (d == 0) ? NF : ((d == 1) ? N : 1);
+            const int st1 = (d == 0) ? N : NF, st2 = (d == 2) ? N : 1;
+            const int tl = qt1 * st1 + qt2 * st2;
+            double upv[5], gpv[5][3], umv[5], gmv[5][3];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                double v0 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int tt = tl + k * sd;
+                    const double l = tb.lag[s][k];
+                    v0 = fma(l, su[a * NQ + tt], v0);
+                    g0 = fma(l, sg[(a * 3 + 0) * NQ + tt], g0);
+                    g1 = fma(l, sg[(a * 3 + 1) * NQ + tt], g1);
+                    g2 = fma(l, sg[(a * 3 + 2) * NQ + tt], g2);
+                }
+                upv[a] = v0;
+                gpv[a][0] = g0;
+                gpv[a][1] = g1;
+                gpv[a][2] = g2;
+            }
+            const double* nt = nbrtr + (((size_t)e * 6 + f) * NF + fq) * 20;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                umv[a] = nt[a];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gmv[a][k] = nt[5 + a * 3 + k];
+            }
+            double nrm[3], JF, Jip[3][3], Jim[3][3], lam_p, lam_m;
+            face_geometry<P, CURVED>(tb, m, e, f, qt1, qt2, nrm, JF, Jip, Jim, lam_p, lam_m);
+            const double sc = tb.w[qt1] * tb.w[qt2] * JF;
+            double* fs = FS + (size_t)fp * 35;
+#pragma unroll 1
+            for (int dir = 0; dir < NDIR; ++dir) {
+                Dual up[5], gxp[5][3], um[5], gxm[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    up[a] = Dual(upv[a], (a == beta && dir == 0) ? 1.0 : 0.0);
+                    um[a] = Dual(umv[a], 0.0);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        gxp[a][k] = Dual(gpv[a][k], (a == beta && dir == k + 1) ? 1.0 : 0.0);
+                        gxm[a][k] = Dual(gmv[a][k], 0.0);
+                    }
+                }
+                Dual fo[20];
+                face_integrand<Dual, NS, FIX_NBR>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, sc, gas, fo);
+                if (dir == 0) {
+#pragma unroll
+                    for (int o = 0; o < (NS ? 20 : 5); ++o) fs[o] = fo[o].d;
+                } else {
+#pragma unroll
+                    for (int o = 0; o < 5; ++o) fs[20 + 5 * (dir - 1) + o] = fo[o].d;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- volume slices (registers, live only from here on): vs[dir][a][k]
+    double vs[NDIR][5][3];
+    double wdet = 0.0;
+    if (active) {
+        double uv[5], gv[5][3];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            uv[a] = su[a * NQ + q];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gv[a][k] = sg[(a * 3 + k) * NQ + q];
+        }
+        double detJ, Ji[3][3];
+        if constexpr (CURVED) {
+            double J[3][3];
+            q1_jac(svtx[es], tb.z[ii[0]], tb.z[ii[1]], tb.z[ii[2]], J);
+            detJ = q1_inv(J, Ji);
+        } else {
+            const double hx = m.h[0], hy = m.h[1], hz = m.h[2];
+            detJ = 0.125 * hx * hy * hz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Ji[k][d] = 0.0;
+            Ji[0][0] = 2.0 / hx;
+            Ji[1][1] = 2.0 / hy;
+            Ji[2][2] = 2.0 / hz;
+        }
+        const double wq = tb.w[ii[0]] * tb.w[ii[1]] * tb.w[ii[2]];
+        wdet = wq * detJ;
+        const double c = -wq * detJ;
+#pragma unroll
+        for (int dir = 0; dir < NDIR; ++dir) {
+            Dual u[5], gx[5][3];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                u[a] = Dual(uv[a], (a == beta && dir == 0) ? 1.0 : 0.0);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gx[a][k] = Dual(gv[a][k], (a == beta && dir == k + 1) ? 1.0 : 0.0);
+            }
+            Dual F[5][3];
+            flux_c(u, gas.gamma - 1.0, F);
+            if constexpr (NS) {
+                Dual g[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        g[a][j] = Ji[0][j] * gx[a][0] + Ji[1][j] * gx[a][1] + Ji[2][j] * gx[a][2];
+                flux_v_acc(u, g, gas, 1.0, F);
+            }
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    vs[dir][a][k] = c * (Ji[k][0] * F[a][0].d + Ji[k][1] * F[a][1].d + Ji[k][2] * F[a][2].d);
+        }
+    }
+    __syncthreads();
+    // ---- columns (beta, hj): slices times basis function hj, spread, test
+    double* sF = S;                     // one round's face integrands, 20 per face point
+    double* sA = S;
+    double* sB = S + 15 * NQ;
+    double* Y1 = S + S_::OFF_U;         // Gauss values no longer needed
+    double* Y2 = S + S_::OFF_G;         // nor the gradients
+    double* H = S + S_::OFF_G + 5 * NQ;
+#pragma unroll 1
+    for (int hj = 0; hj < NQ; ++hj) {
+        const int tj = sinv[hj];
+        const int jj[3] = {tj / NF, (tj / N) % N, tj % N};
+        const int col = beta * NQ + hj;
+        double Ad[5][3], Bd[5];
+        if (active) {
+            const double p0 = tb.V[ii[0]][jj[0]], p1 = tb.V[ii[1]][jj[1]], p2 = tb.V[ii[2]][jj[2]];
+            const double phi = p0 * p1 * p2;
+            const double dphi[3] = {tb.Vd[ii[0]][jj[0]] * p1 * p2, p0 * tb.Vd[ii[1]][jj[1]] * p2,
+                                    p0 * p1 * tb.Vd[ii[2]][jj[2]]};
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    double acc = vs[0][a][k] * phi;
+                    if constexpr (NS) {
+                        acc = fma(vs[1][a][k], dphi[0], acc);
+                        acc = fma(vs[2][a][k], dphi[1], acc);
+                        acc = fma(vs[3][a][k], dphi[2], acc);
+                    }
+                    Ad[a][k] = acc;
+                }
+                Bd[a] = (a == beta) ? shift * wdet * phi : 0.0;
+            }
+        }
+        for (int r = 0; r * NQ < NFP; ++r) {
+            const int fp = r * NQ + q;
+            if (active && fp < NFP) {
+                const int f = fp / NF, fq = fp % NF;
+                const int d = f >> 1, s = f & 1;
+                double bv, bg[3];
+                face_basis<N>(tb, d, s, fq / N, fq % N, tj, bv, bg);
+                const double* fs = FS + (size_t)fp * 35;
+                double* so = sF + q * 20;
+#pragma unroll
+                for (int o = 0; o < 5; ++o) {
+                    double acc = fs[o] * bv;
+                    if constexpr (NS) {
+                        acc = fma(fs[20 + o], bg[0], acc);
+                        acc = fma(fs[25 + o], bg[1], acc);
+                        acc = fma(fs[30 + o], bg[2], acc);
+                    }
+                    so[o] = acc;
+                }
+                if constexpr (NS) {
+#pragma unroll
+                    for (int o = 5; o < 20; ++o) so[o] = fs[o] * bv;
+                }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int fl = 0; fl < N; ++fl) {
+                    const int f = r * N + fl;
+                    if (f >= 6) break;
+                    const int d = f >> 1, s = f & 1;
+                    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+                    const double l = tb.lag[s][ii[d]];
+                    const double* fo = sF + (fl * NF + ii[t1] * N + ii[t2]) * 20;
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) {
+                        Bd[a] = fma(l, fo[a], Bd[a]);
+                        if constexpr (NS) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) Ad[a][k] = fma(l, fo[5 + a * 3 + k], Ad[a][k]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sA[(a * 3 + k) * NQ + q] = Ad[a][k];
+                sB[a * NQ + q] = Bd[a];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                double acc = sB[a * NQ + q];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < N; ++j)
+                        acc = fma(tb.D[j][ii[k]], sA[(a * 3 + k) * NQ + tix_dir<N>(k, j, ii)], acc);
+                H[a * NQ + q] = acc;
+            }
+        }
+        __syncthreads();
+        if (active) sweep<N, 5, true>(tb.V, H, Y1, 0, ii, q);
+        __syncthreads();
+        if (active) sweep<N, 5, true>(tb.V, Y1, Y2, 1, ii, q);
+        __syncthreads();
+        if (active) {
+            const int pm = perm[q];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc = fma(tb.V[j][ii[2]], Y2[a * NQ + tix_dir<N>(2, j, ii)], acc);
+                out[((size_t)e * NB + col) * ld + a * NQ + pm] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 namespace {
 template <int P, bool SELF>
 hipError_t launch_diag_k(const DGArgs& a, const double* W, double shift, double* blocks, int ld, double* nbrtr,
@@ -2056,6 +2377,30 @@ hipError_t launch_diag_k(const DGArgs& a, const double* W, double shift, double*
         else hipLaunchKernelGGL((diag_kernel<P, false, false, SELF>), grid, block, 0, s, a.m, a.g, W, nbrtr, shift, blocks, ld);
     }
     return hipGetLastError();
+}
+
+template <int P, bool NS, bool CURVED>
+hipError_t launch_diag_slices_k(const DGArgs& a, const double* W, double shift, double* blocks, int ld,
+                                const double* nbrtr, hipStream_t s) {
+    constexpr int EPB = LaunchS<P>::EPB;
+    const size_t lds = (size_t)EPB * SzS<P>::TOT * sizeof(double);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)diag_slices_kernel<P, NS, CURVED>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((a.m.ne + EPB - 1) / EPB, 5), block(EPB * SzS<P>::NQ);
+    hipLaunchKernelGGL((diag_slices_kernel<P, NS, CURVED>), grid, block, lds, s, a.m, a.g, W, nbrtr, shift, blocks,
+                       ld);
+    return hipGetLastError();
+}
+template <int P>
+hipError_t launch_diag_slices(const DGArgs& a, const double* W, double shift, double* blocks, int ld,
+                              const double* nbrtr, bool curved, hipStream_t s) {
+    if (a.ns) return curved ? launch_diag_slices_k<P, true, true>(a, W, shift, blocks, ld, nbrtr, s)
+                            : launch_diag_slices_k<P, true, false>(a, W, shift, blocks, ld, nbrtr, s);
+    return curved ? launch_diag_slices_k<P, false, true>(a, W, shift, blocks, ld, nbrtr, s)
+                  : launch_diag_slices_k<P, false, false>(a, W, shift, blocks, ld, nbrtr, s);
 }
 
 template <int P>
@@ -2071,7 +2416,7 @@ hipError_t launch_diag_p(const DGArgs& a, const double* W, double shift, double*
     const bool curved = a.m.vtx != nullptr;
     const bool self = a.m.nx == 1 || a.m.ny == 1 || a.m.nz == 1;
     if (self) return launch_diag_k<P, true>(a, W, shift, blocks, ld, nbrtr, grid, block, curved, s);
-    return launch_diag_k<P, false>(a, W, shift, blocks, ld, nbrtr, grid, block, curved, s);
+    return launch_diag_slices<P>(a, W, shift, blocks, ld, nbrtr, curved, s);
 }
 }  // namespace
 
