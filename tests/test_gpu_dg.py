@@ -122,11 +122,16 @@ def test_mass_and_projection(p, curved):
     assert _rel(W, D.project(vals)) < 1e-13
 
 
-@pytest.mark.parametrize("n,p,curved", [((3, 2, 2), 1, True), ((2, 3, 2), 2, False), ((3, 1, 2), 2, True),
-                                        ((2, 2, 2), 3, True)])
-def test_diag_blocks_parity(n, p, curved):
-    print("blocks", n, p, curved, flush=True)
-    ctx, D = _case(n, p, 0.02, curved)
+# Meshes with no single-element axis take the Jacobian-slice kernel (NS: four
+# derivative directions; Euler, mu = 0: one), those with one (3 x 1 x 2) the
+# per-column kernel.
+@pytest.mark.parametrize("n,p,curved,mu", [((3, 2, 2), 1, True, 0.02), ((2, 3, 2), 2, False, 0.02),
+                                           ((3, 1, 2), 2, True, 0.02), ((2, 2, 2), 3, True, 0.02),
+                                           ((2, 3, 2), 1, False, 0.02), ((3, 2, 2), 1, True, 0.0),
+                                           ((2, 2, 3), 2, False, 0.0), ((2, 2, 2), 3, False, 0.0)])
+def test_diag_blocks_parity(n, p, curved, mu):
+    print("blocks", n, p, curved, mu, flush=True)
+    ctx, D = _case(n, p, mu, curved)
     W = inputs.random_state(ctx.ne, p, seed=31)
     a = 12.0
     B = ctx.assemble_diag(_dev(W), a).cpu().numpy()        # [e][col][row]
@@ -136,15 +141,16 @@ def test_diag_blocks_parity(n, p, curved):
     assert np.abs(Bg - Bo).max() < 1e-11 * np.abs(Bo).max()
 
 
-@pytest.mark.parametrize("n", [(2, 2, 2), (3, 2, 2)])
-def test_diag_blocks_p4_sampled_columns(n):
-    """p = 4 diagonal blocks on curved meshes with no single-element axis (the
-    block kernel of the 16^3 workloads): 24 seeded columns of every block,
-    including the first and last, against the oracle's complex-step columns,
-    element by element (1e-12 of the largest entry).  The oracle's full
-    625-column blocks would take minutes."""
-    print("blocks p=4", n, flush=True)
-    ctx, D = _case(n, 4, 0.02, True, amp=0.1)
+@pytest.mark.parametrize("n,curved,mu", [((2, 2, 2), True, 0.02), ((3, 2, 2), True, 0.02), ((2, 2, 2), False, 0.0)])
+def test_diag_blocks_p4_sampled_columns(n, curved, mu):
+    """p = 4 diagonal blocks on meshes with no single-element axis (the
+    block kernel of the 16^3 workloads; the last case Euler on a straight
+    mesh): 24 seeded columns of every block, including the first and last,
+    against the oracle's complex-step columns, element by element (1e-12 of
+    the largest entry).  The oracle's full 625-column blocks would take
+    minutes."""
+    print("blocks p=4", n, curved, mu, flush=True)
+    ctx, D = _case(n, 4, mu, curved, amp=0.1)
     W = inputs.random_state(ctx.ne, 4, seed=33)
     a = 12.0
     nb = 5 * ctx.nv
