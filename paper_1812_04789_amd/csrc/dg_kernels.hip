@@ -263,6 +263,9 @@ __device__ __forceinline__ void face_integrand(const T up[5], const T gxp[5][3],
     } else {
 #pragma unroll
         for (int a = 0; a < 5; ++a) fo[a] = sc * Fn[a];
+        // no viscous flux: no terms on the reference gradients of the test functions
+#pragma unroll
+        for (int k = 5; k < 20; ++k) fo[k] = T(0.0);
     }
 }
 

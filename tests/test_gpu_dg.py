@@ -87,15 +87,18 @@ def test_jvp_parity(n, p, curved):
     assert torch.count_nonzero(z).item() == 0
 
 
-@pytest.mark.parametrize("n,p,curved", [((3, 2, 2), 1, True), ((3, 2, 2), 2, False), ((2, 3, 2), 3, True),
-                                         ((3, 1, 2), 2, True), ((2, 2, 2), 4, False), ((2, 2, 2), 4, True)])
-def test_matrix_based_product(n, p, curved):
+@pytest.mark.parametrize("n,p,curved,mu", [((3, 2, 2), 1, True, 0.02), ((3, 2, 2), 2, False, 0.02),
+                                            ((2, 3, 2), 3, True, 0.02), ((3, 1, 2), 2, True, 0.02),
+                                            ((2, 2, 2), 4, False, 0.02), ((2, 2, 2), 4, True, 0.02),
+                                            ((3, 2, 2), 2, True, 0.0)])
+def test_matrix_based_product(n, p, curved, mu):
     """The assembled operator (diagonal blocks + fine face-coupling blocks in
     the 7-block product) applied to v equals the oracle's exact product
     shift M v + (dR/dW) v (both exact: 1e-12), on meshes with and without a
-    single-element axis; before assembly the product is refused."""
-    print("matrix-based", n, p, curved, flush=True)
-    ctx, D = _case(n, p, 0.02, curved)
+    single-element axis; before assembly the product is refused.  mu = 0:
+    Euler."""
+    print("matrix-based", n, p, curved, mu, flush=True)
+    ctx, D = _case(n, p, mu, curved)
     W = inputs.random_state(ctx.ne, p, seed=41 + p)
     v = inputs.random_vector(ctx.ne, p, seed=42 + p)
     a = 25.0

@@ -164,18 +164,20 @@ def test_vcycle_graph_replays_match_eager(cmf, cprec):
         assert torch.equal(g2, z2), i
 
 
-@pytest.mark.parametrize("p,pc,curved", [(2, 1, True), (3, 1, False), (3, 2, True), (4, 1, True), (4, 2, True),
-                                         (4, 4, True)])
-def test_coarse_face_blocks_are_jacobian_blocks(p, pc, curved):
+@pytest.mark.parametrize("p,pc,curved,mu", [(2, 1, True, 0.02), (3, 1, False, 0.02), (3, 2, True, 0.02),
+                                            (4, 1, True, 0.02), (4, 2, True, 0.02), (4, 4, True, 0.02),
+                                            (2, 1, False, 0.0), (3, 3, True, 0.0)])
+def test_coarse_face_blocks_are_jacobian_blocks(p, pc, curved, mu):
     """Face-coupling blocks of the inherited coarse operator equal the exact
     Jacobian columns: perturbing a coarse mode of the neighbour across face f
     changes R_e only through face f (3^3 mesh: each neighbour is across one
     face).  p = 4 with pc = 1, 2 are the coarse levels of the curved 16^3
     workload; pc = p are the fine face blocks of the matrix-based product.
-    Compared entry by entry (1e-12 of the largest entry of the column)."""
-    print("face blocks", p, pc, curved, flush=True)
+    Compared entry by entry (1e-12 of the largest entry of the column).  The
+    mu = 0 cases are Euler (no viscous or gradient-test terms)."""
+    print("face blocks", p, pc, curved, mu, flush=True)
     n = (3, 3, 3)
-    ctx, D = _case(n, p, 0.02, curved)
+    ctx, D = _case(n, p, mu, curved)
     W = inputs.random_state(ctx.ne, p, seed=61)
     off = ctx.assemble_coarse(_dev(W), pc).cpu().numpy()      # [e][f][col][row]
     nvc = (pc + 1) ** 3
