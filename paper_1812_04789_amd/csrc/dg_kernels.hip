@@ -105,10 +105,12 @@ struct Lay;
 template <int P>
 struct Lay<P, true> {
     static constexpr int NQ = Sz<P>::NQ;
-    // [0, 25 NQ): interpolation buffers (15 NQ) | one round: neighbour collapse
-    //             (10 NQ) + first tangential sweep (15 NQ), then face integrands
-    //             (20 NQ) | test A, B (20 NQ)
-    static constexpr int OFF_U = 25 * NQ;                                  // Gauss values (5 NQ)
+    // [0, 20 NQ): interpolation buffers (15 NQ) | one round: neighbour collapse
+    //             (10 NQ) + first tangential sweep (15 NQ, variables 0-2 after
+    //             the collapse, 3-4 over the consumed collapse of 0-2), then
+    //             face integrands (20 NQ) | test A, B (20 NQ).  40 NQ in all:
+    //             eight elements per CU at degree 3.
+    static constexpr int OFF_U = 20 * NQ;                                  // Gauss values (5 NQ)
     static constexpr int OFF_G = OFF_U + 5 * NQ;                           // Gauss ref. gradients (15 NQ)
     static constexpr int OFF_E = OFF_U;                                    // test-back (15 NQ, over the dead values and gradients)
     static constexpr int TOT = OFF_U + 20 * NQ;
@@ -383,17 +385,19 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
         // slot q = (face fl of the round, face point fq) in every stage:
         //   1  neighbour: collapse of its modal data along the normal (value and
         //      normal derivative at the shared face) -> sC;
-        //   2  neighbour: first tangential sweep -> sE;
+        //   2  neighbour: first tangential sweep -> sE, variables 0-2 into
+        //      [10 NQ, 19 NQ), then (after a barrier) 3-4 over the collapse of
+        //      0-2 in [0, 6 NQ);
         //   3  both traces with reference gradients (own ones from the stored
         //      Gauss values and gradients), then the face integrand (registers);
-        //   4  integrands -> sF (components 0-9 over sC at once, 10-19 over sE
-        //      after the barrier), spread onto the Gauss lines.
+        //   4  after a barrier, integrands -> sF over sC and sE, spread onto
+        //      the Gauss lines.
         // Staging is component-major (sC[c * NQ + slot], ...): consecutive
         // threads touch consecutive doubles, and only one round's neighbour
         // data is held at a time.
         T* sC = S;                    // 10 NQ
-        T* sE = S + 10 * NQ;          // 15 NQ
         T* sF = S;                    // 20 NQ
+        auto sE = [&](int a) -> T* { return (a < 3) ? S + (10 + 3 * a) * NQ : S + 3 * (a - 3) * NQ; };
 #pragma unroll 1
         for (int r = 0; r * NQ < 6 * NF; ++r) {
             const int fp = r * NQ + q;
@@ -424,22 +428,29 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
                 }
             }
             __syncthreads();
+            auto sweep1 = [&](int a) {
+                T e0 = 0.0, e0d = 0.0, e1 = 0.0;
+#pragma unroll
+                for (int b2 = 0; b2 < N; ++b2) {
+                    const int src = fl * NF + b2 * N + qt2;
+                    const T cv0 = sC[(a * 2 + 0) * NQ + src];
+                    e0 = fma(tb.V[qt1][b2], cv0, e0);
+                    e0d = fma(tb.Vd[qt1][b2], cv0, e0d);
+                    e1 = fma(tb.V[qt1][b2], sC[(a * 2 + 1) * NQ + src], e1);
+                }
+                T* se = sE(a);
+                se[0 * NQ + q] = e0;
+                se[1 * NQ + q] = e0d;
+                se[2 * NQ + q] = e1;
+            };
             if (on) {
 #pragma unroll
-                for (int a = 0; a < 5; ++a) {
-                    T e0 = 0.0, e0d = 0.0, e1 = 0.0;
+                for (int a = 0; a < 3; ++a) sweep1(a);
+            }
+            __syncthreads();
+            if (on) {
 #pragma unroll
-                    for (int b2 = 0; b2 < N; ++b2) {
-                        const int src = fl * NF + b2 * N + qt2;
-                        const T cv0 = sC[(a * 2 + 0) * NQ + src];
-                        e0 = fma(tb.V[qt1][b2], cv0, e0);
-                        e0d = fma(tb.Vd[qt1][b2], cv0, e0d);
-                        e1 = fma(tb.V[qt1][b2], sC[(a * 2 + 1) * NQ + src], e1);
-                    }
-                    sE[(a * 3 + 0) * NQ + q] = e0;
-                    sE[(a * 3 + 1) * NQ + q] = e0d;
-                    sE[(a * 3 + 2) * NQ + q] = e1;
-                }
+                for (int a = 3; a < 5; ++a) sweep1(a);
             }
             __syncthreads();
             T fo[20];
@@ -448,14 +459,15 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
                     T v0 = 0.0, vt1 = 0.0, vt2 = 0.0, vd = 0.0;
+                    const T* se = sE(a);
 #pragma unroll
                     for (int c = 0; c < N; ++c) {
                         const int src = fl * NF + qt1 * N + c;
-                        const T ev0 = sE[(a * 3 + 0) * NQ + src];
+                        const T ev0 = se[0 * NQ + src];
                         v0 = fma(tb.V[qt2][c], ev0, v0);
-                        vt1 = fma(tb.V[qt2][c], sE[(a * 3 + 1) * NQ + src], vt1);
+                        vt1 = fma(tb.V[qt2][c], se[1 * NQ + src], vt1);
                         vt2 = fma(tb.Vd[qt2][c], ev0, vt2);
-                        vd = fma(tb.V[qt2][c], sE[(a * 3 + 2) * NQ + src], vd);
+                        vd = fma(tb.V[qt2][c], se[2 * NQ + src], vd);
                     }
                     um[a] = v0;
 #pragma unroll
@@ -538,16 +550,11 @@ __device__ __forceinline__ void dg_element(const MeshDev& m, const Gas& gas, con
                 }
                 face_integrand<T, NS>(up, gxp, um, gxm, nrm, Jip, Jim, lam_p, lam_m, tb.w[qt1] * tb.w[qt2] * JF, gas,
                                       fo);
-                // the first ten components go over the (dead) collapse at once
-#pragma unroll
-                for (int k = 0; k < (NS ? 10 : 5); ++k) sF[k * NQ + q] = fo[k];
             }
-            __syncthreads();
-            if constexpr (NS) {
-                if (on) {
+            __syncthreads();          // every thread has read its traces from sE
+            if (on) {
 #pragma unroll
-                    for (int k = 10; k < 20; ++k) sF[k * NQ + q] = fo[k];
-                }
+                for (int k = 0; k < (NS ? 20 : 5); ++k) sF[k * NQ + q] = fo[k];
             }
             __syncthreads();
             if (active) {
