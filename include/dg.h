@@ -302,8 +302,10 @@ dg_status dg_use_graphs(dg_ctx* ctx, int enable);
  * written blocks, PLU (2/3) n^3 flops and one read + write of the block,
  * block-Jacobi apply one read of the factors (or inverse) and 16 B per vector
  * entry, block-sparse coarse product its 7 blocks per element and 16 B per
- * entry, Arnoldi step j 32 (j + 1) B per entry: two passes of dots and
- * updates) since the last clear, then clears.  The fine-level (level 0)
+ * entry, Arnoldi step j 24 (j + 1) + 32 B per entry: the dots, the first
+ * update with the second-pass dots and the norm, the second update with the
+ * normalisation; 16 (j + 1) + 32 when the first dots are taken inside the
+ * coarse product) since the last clear, then clears.  The fine-level (level 0)
  * block-Jacobi apply is its own family; coarse-level applies form another.
  * All arrays have DG_K_COUNT entries (host memory). */
 enum { DG_K_RESIDUAL = 0, DG_K_JVP_FD = 1, DG_K_JVP_EXACT = 2, DG_K_DIAG_BLOCKS = 3, DG_K_LU = 4,
