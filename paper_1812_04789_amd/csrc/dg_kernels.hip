@@ -2070,12 +2070,19 @@ __global__ void __launch_bounds__((LaunchD<P>::EPB * SzD<P>::NQ))
 // and reference gradients, spread onto the Gauss lines and tested exactly
 // as in the per-column kernel.  Four dual evaluations per point and beta
 // instead of one per column.
+// LDS per element slot, 35 NQ + the face slices: before the columns, modal
+// data and the two interpolation sweeps in [0, 15 NQ), Gauss values at
+// OFF_U, reference gradients at OFF_G; for the columns, a round's face
+// integrands and then the test inputs A, B in [0, 20 NQ), H and the two test
+// sweeps at OFF_H (over the dead values and gradients).  Two workgroups per
+// CU at degree 4.
 template <int P>
 struct SzS {
     static constexpr int N = P + 1, NQ = N * N * N, NF = N * N, NFP = 6 * NF;
-    static constexpr int OFF_U = 20 * NQ;        // Gauss values (5NQ); then the first test sweep
-    static constexpr int OFF_G = 25 * NQ;        // reference gradients (15NQ); then the second test sweep and H
-    static constexpr int OFF_FS = 40 * NQ;       // face slices, 35 per face point
+    static constexpr int OFF_U = 15 * NQ;        // Gauss values (5NQ)
+    static constexpr int OFF_G = 20 * NQ;        // reference gradients (15NQ)
+    static constexpr int OFF_H = 20 * NQ;        // H, then the two test sweeps (5NQ each)
+    static constexpr int OFF_FS = 35 * NQ;       // face slices, 35 per face point
     static constexpr int TOT = OFF_FS + 35 * NFP;
 };
 template <int P> struct LaunchS { static constexpr int EPB = (P == 1) ? 4 : ((P == 2) ? 2 : 1); };
@@ -2260,9 +2267,9 @@ __global__ void __launch_bounds__((LaunchS<P>::EPB * SzS<P>::NQ))
     double* sF = S;                     // one round's face integrands, 20 per face point
     double* sA = S;
     double* sB = S + 15 * NQ;
-    double* Y1 = S + S_::OFF_U;         // Gauss values no longer needed
-    double* Y2 = S + S_::OFF_G;         // nor the gradients
-    double* H = S + S_::OFF_G + 5 * NQ;
+    double* H = S + S_::OFF_H;          // Gauss values and gradients no longer needed
+    double* Y1 = H + 5 * NQ;
+    double* Y2 = Y1 + 5 * NQ;
 #pragma unroll 1
     for (int hj = 0; hj < NQ; ++hj) {
         const int tj = sinv[hj];
